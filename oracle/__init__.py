@@ -1,0 +1,179 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes binding of the double-precision CPU oracle.
+
+The oracle (spotfit_oracle.c, plain serial C in double precision) is the
+reference the HIP path is checked against.  Only the tests, the smoke check and
+the CPU-baseline leg of the benchmark may import this module; the product
+package never does.  It shares no code with the HIP path.
+
+Parity status: see the header of spotfit_oracle.h (what pins each function).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "spotfit_oracle.c")
+
+MAX_ITER, MAX_ERROR, MIN_DELTA, MIN_STEP, NOT_CONVERGED, BAD_INPUT = range(6)
+STATUS_NAMES = ["MAX_ITER", "MAX_ERROR", "MIN_DELTA", "MIN_STEP", "NOT_CONVERGED", "BAD_INPUT"]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("max_iter", ctypes.c_int32),
+        ("max_error_per_px", ctypes.c_double),
+        ("min_delta", ctypes.c_double),
+        ("min_step_rel", ctypes.c_double),
+        ("lambda0_exp10", ctypes.c_int32),
+        ("lambda_max_exp10", ctypes.c_int32),
+        ("tie_tau", ctypes.c_double),
+        ("sigma_min", ctypes.c_double),
+        ("sigma_max_frac", ctypes.c_double),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("params", ctypes.c_double * 6),
+        ("chi2", ctypes.c_double),
+        ("iters", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("n_grad", ctypes.c_int32),
+        ("n_trial", ctypes.c_int32),
+        ("margin_chi", ctypes.c_double),
+        ("margin_step", ctypes.c_double),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc: baseline x86-64, no fast-math, no FMA contraction."""
+    if force or not os.path.exists(LIB_PATH) or \
+            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=gnu99", "-ffp-contract=off",
+                        "-fno-fast-math", "-Wall", "-o", tmp, SRC_PATH, "-lm", "-lpthread"],
+                       check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.orc_eval.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
+                               dp, dp, dp, dp]
+        L.orc_eval.restype = ctypes.c_int
+        L.orc_solve.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_solve.restype = ctypes.c_int
+        L.orc_pow10.argtypes = [ctypes.c_int]
+        L.orc_pow10.restype = ctypes.c_double
+        L.orc_fit_spot.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_float), ctypes.POINTER(Opts),
+                                   ctypes.POINTER(Result)]
+        vp = ctypes.c_void_p
+        L.orc_fit_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int64,
+                                    ctypes.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp,
+                                    ctypes.c_int]
+        L.orc_fit_batch.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().orc_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def nparams(model: int) -> int:
+    return 3 if model == 0 else 4
+
+
+def eval_spot(g, w: int, h: int, model: int, p, grad: bool = True, want_J: bool = False):
+    """One model evaluation.  Returns dict(alpha, beta, chi2, A, b, J, rc)."""
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(-1))
+    assert g.size == w * h
+    n = nparams(model)
+    p = np.ascontiguousarray(np.asarray(p, dtype=np.float64)[:n])
+    out3 = np.zeros(3)
+    A = np.zeros((n, n))
+    b = np.zeros(n)
+    J = np.zeros((w * h, n)) if want_J else None
+    rc = lib().orc_eval(_dp(g), w, h, model, _dp(p), int(grad), _dp(out3), _dp(A), _dp(b),
+                        _dp(J) if J is not None else None)
+    return dict(alpha=out3[0], beta=out3[1], chi2=out3[2], A=A, b=b, J=J, rc=rc)
+
+
+def solve(A, b, lam: float):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    d = np.zeros(len(b))
+    rc = lib().orc_solve(_dp(A), _dp(b), len(b), float(lam), _dp(d))
+    return d, rc
+
+
+def pow10(k: int) -> float:
+    return lib().orc_pow10(int(k))
+
+
+def fit_spot(g, w: int, h: int, model: int, init4, opts: Optional[Opts] = None) -> dict:
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(-1))
+    init4 = np.ascontiguousarray(np.asarray(init4, dtype=np.float32).reshape(4))
+    o = opts if opts is not None else default_opts()
+    r = Result()
+    lib().orc_fit_spot(_dp(g), w, h, model, init4.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                       ctypes.byref(o), ctypes.byref(r))
+    return dict(params=np.array(r.params[:]), chi2=r.chi2, iters=r.iters, status=r.status,
+                n_grad=r.n_grad, n_trial=r.n_trial, margin_chi=r.margin_chi,
+                margin_step=r.margin_step)
+
+
+def fit_batch(batch, opts: Optional[Opts] = None, threads: int = 1) -> dict:
+    """Fit every spot of a spotgen.SpotBatch; returns a dict of numpy arrays."""
+    n = batch.n
+    o = opts if opts is not None else default_opts()
+    data = np.ascontiguousarray(batch.data)
+    if data.dtype == np.uint16:
+        dtype = 0
+    elif data.dtype == np.float32:
+        dtype = 1
+    else:
+        raise TypeError(data.dtype)
+    sizes = np.ascontiguousarray(batch.sizes, dtype=np.uint8)
+    offs = np.ascontiguousarray(batch.offsets, dtype=np.int64)
+    init = np.ascontiguousarray(batch.init, dtype=np.float32)
+    out = dict(params=np.zeros((n, 6)), chi2=np.zeros(n), iters=np.zeros(n, np.int32),
+               status=np.zeros(n, np.int32), n_grad=np.zeros(n, np.int32),
+               n_trial=np.zeros(n, np.int32), margin_chi=np.zeros(n), margin_step=np.zeros(n))
+    if n == 0:
+        return out
+    rc = lib().orc_fit_batch(data.ctypes.data, dtype, sizes.ctypes.data, offs.ctypes.data,
+                             init.ctypes.data, n, ctypes.byref(o),
+                             *(out[k].ctypes.data for k in ("params", "chi2", "iters", "status",
+                                                            "n_grad", "n_trial", "margin_chi",
+                                                            "margin_step")), int(threads))
+    if rc != 0:
+        raise RuntimeError(f"orc_fit_batch failed ({rc})")
+    return out

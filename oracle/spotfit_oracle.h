@@ -1,0 +1,92 @@
+/*
+ * spotfit_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, serial, double-precision CPU reference of the implicit-amplitude
+ * Levenberg-Marquardt fit of 2D Gaussian spots (Leutenegger & Weber,
+ * "Least-squares fitting of Gaussian spots on graphics processing units").
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may call it.  It shares no code, header, table or helper with the HIP path.
+ *
+ * Parity status per function (what pins it; see the tests):
+ *   orc_eval   Eqs. 5-6 pinned to a textbook linear least-squares solve,
+ *              Eqs. 7-9 and 11 pinned to central finite differences,
+ *              the gradient pinned to the envelope identity.
+ *   orc_solve  pinned to a generic dense solve of the damped system (Eq. 14).
+ *   orc_fit_*  pinned by noise-free recovery, by equality with an explicit
+ *              five-parameter least-squares fit (scipy), by brute-force grid
+ *              search on tiny spots, and statistically by Table 1 / Fig. 8.
+ *   The status codes, the MaxError threshold "A/3", the limit() box and the
+ *   chi^2 normalisation are the paper's unspecified details: parity unpinned.
+ */
+#ifndef SPOTFIT_ORACLE_H
+#define SPOTFIT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_SYM = 0, ORC_ELL = 1 };
+enum { ORC_MAX_ITER = 0, ORC_MAX_ERROR = 1, ORC_MIN_DELTA = 2, ORC_MIN_STEP = 3,
+       ORC_NOT_CONVERGED = 4, ORC_BAD_INPUT = 5 };
+
+typedef struct {
+  int32_t max_iter;          /* iteration budget (paper: 20)                          */
+  double  max_error_per_px;  /* MaxError iff chi^2 < max_error_per_px * N  ("A/3")    */
+  double  min_delta;         /* MinDelta iff chi*(1-min_delta) < Chi   (paper: 1e-6)  */
+  double  min_step_rel;      /* MinStep iff all |delta_j| < min_step_rel*|p_j| (1e-4) */
+  int32_t lambda0_exp10;     /* initial damping 10^k0 (paper: 0.01 -> -2)             */
+  int32_t lambda_max_exp10;  /* retries while k < this (paper: 10^4 -> 4)             */
+  double  tie_tau;           /* relative tie band for chi^2 comparisons (0 = verbatim) */
+  double  sigma_min;         /* limit(): sigma >= sigma_min                           */
+  double  sigma_max_frac;    /* limit(): sigma <= sigma_max_frac * max(w, h)          */
+} orc_opts;
+
+typedef struct {
+  double  params[6];   /* x, y, sigma_x, sigma_y, alpha, beta (sym: sigma_y = sigma_x) */
+  double  chi2;        /* raw sum of squared residuals at params                        */
+  int32_t iters;       /* loop passes started                                          */
+  int32_t status;      /* ORC_* code                                                   */
+  int32_t n_grad;      /* evaluations with derivatives                                 */
+  int32_t n_trial;     /* evaluations without derivatives (trial steps)               */
+  double  margin_chi;  /* smallest relative margin of any chi^2 comparison taken       */
+  double  margin_step; /* smallest relative margin of any step-size comparison taken   */
+} orc_result;
+
+void orc_default_opts(orc_opts* o);
+
+/* Number of shaping parameters of a model (3 or 4), or 0 if unknown. */
+int orc_nparams(int model);
+
+/* One evaluation of the reduced model at shaping parameters p (Eqs. 2-11).
+ * g: w*h pixel values (row-major), p: n shaping params.
+ * out3 = (alpha_hat, beta_hat, chi^2).  If want_grad: A (n*n, row-major) = J^T J,
+ * bvec (n) = J^T (g - h) and, when J != NULL, J (N*n) = d r_k / d p_j with
+ * r = h - g.  Returns 0, or 1 when N*sum f^2 - (sum f)^2 is not positive or the
+ * result is not finite (then chi^2 = NaN). */
+int orc_eval(const double* g, int w, int h, int model, const double* p, int want_grad,
+             double* out3, double* A, double* bvec, double* J);
+
+/* Damped step (Eq. 14): (A + lam*diag(A)) delta = bvec by Cholesky.
+ * Returns 0, or 1 (delta set to NaN) if the matrix is not positive definite. */
+int orc_solve(const double* A, const double* bvec, int n, double lam, double* delta);
+
+/* 10^k from its definition (exact for |k| <= 22). */
+double orc_pow10(int k);
+
+/* Whole fit of one spot from init4 = (x, y, sigma_x, sigma_y). */
+void orc_fit_spot(const double* g, int w, int h, int model, const float* init4,
+                  const orc_opts* o, orc_result* res);
+
+/* Batch driver over the ragged layout; dtype 0 = uint16, 1 = float32.
+ * Every output array has n entries (params: n*6).  Spots are split into
+ * contiguous static chunks over n_threads POSIX threads. Returns 0 or -1. */
+int orc_fit_batch(const void* data, int dtype, const uint8_t* sizes, const int64_t* offsets,
+                  const float* init, int64_t n, const orc_opts* o, double* params,
+                  double* chi2, int32_t* iters, int32_t* status, int32_t* n_grad,
+                  int32_t* n_trial, double* margin_chi, double* margin_step, int n_threads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

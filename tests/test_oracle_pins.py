@@ -1,0 +1,334 @@
+"""Pins of the double-precision oracle against things other than itself.
+
+Each test checks the oracle against what the paper or the mathematics fixes:
+a textbook linear least-squares solve (Eqs. 3-6), finite differences
+(Eqs. 7-9, 11), a generic dense solve (Eq. 14), noise-free recovery, an
+explicit five-parameter fit done by scipy, brute-force grid search on tiny
+spots, model special cases, and the paper's own Table 1 and Fig. 8 statistics.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+import oracle
+import spotgen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _grid_xy(w, h):
+    k = np.arange(w * h)
+    return (k % w).astype(float), (k // w).astype(float)
+
+
+def _profile_np(w, h, model, p):
+    # the generator-independent profile used only to build inputs for the pins
+    x, y = _grid_xy(w, h)
+    if model == 0:
+        return np.exp(-((x - p[0]) ** 2 + (y - p[1]) ** 2) / (2 * p[2] ** 2))
+    return np.exp(-(x - p[0]) ** 2 / (2 * p[2] ** 2) - (y - p[1]) ** 2 / (2 * p[3] ** 2))
+
+
+def _lstsq_residual(g, w, h, model, p):
+    """r = h - g with (alpha, beta) from numpy's least-squares solver."""
+    f = _profile_np(w, h, model, p)
+    M = np.stack([f, np.ones_like(f)], 1)
+    coef, *_ = np.linalg.lstsq(M, g, rcond=None)
+    return M @ coef - g, coef
+
+
+def _rand_spot(rng, w, h, model, noisy=True):
+    n = 3 if model == 0 else 4
+    p = np.array([(w - 1) / 2 + rng.uniform(-1, 1), (h - 1) / 2 + rng.uniform(-1, 1),
+                  rng.uniform(1.1, 2.5), rng.uniform(1.1, 2.5)])[:n]
+    if model == 0:
+        p = p[:3]
+    lam = rng.uniform(200, 3000) * _profile_np(w, h, model, p) + rng.uniform(10, 300)
+    g = rng.poisson(lam).astype(float) if noisy else lam
+    return g, p
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_amplitudes_equal_linear_least_squares(model):
+    """Eqs. 5-6: closed-form alpha_hat, beta_hat and chi^2 = lstsq of g on [f, 1]."""
+    rng = np.random.default_rng(1)
+    for trial in range(20):
+        w, h = [(7, 7), (11, 9), (15, 15), (32, 32)][trial % 4]
+        g, p = _rand_spot(rng, w, h, model)
+        pt = p + rng.normal(0, 0.2, size=p.shape)  # away from the minimum too
+        pt[2:] = np.abs(pt[2:]) + 0.5
+        e = oracle.eval_spot(g, w, h, model, pt, grad=False)
+        r, coef = _lstsq_residual(g, w, h, model, pt)
+        assert e["rc"] == 0
+        assert e["alpha"] == pytest.approx(coef[0], rel=1e-11, abs=1e-9)
+        assert e["beta"] == pytest.approx(coef[1], rel=1e-11, abs=1e-9)
+        assert e["chi2"] == pytest.approx(float(r @ r), rel=1e-11)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_jacobian_matches_finite_differences(model):
+    """Eqs. 7-9 and 11: J = d(h - g)/dp, by central differences of the lstsq residual."""
+    rng = np.random.default_rng(2)
+    for trial in range(12):
+        w, h = [(9, 9), (15, 15), (21, 13)][trial % 3]
+        g, p = _rand_spot(rng, w, h, model)
+        pt = p + rng.normal(0, 0.15, size=p.shape)
+        e = oracle.eval_spot(g, w, h, model, pt, grad=True, want_J=True)
+        n = len(pt)
+        Jfd = np.zeros((w * h, n))
+        for j in range(n):
+            hstep = 1e-5 * max(1.0, abs(pt[j]))
+            pp, pm = pt.copy(), pt.copy()
+            pp[j] += hstep
+            pm[j] -= hstep
+            Jfd[:, j] = (_lstsq_residual(g, w, h, model, pp)[0] -
+                         _lstsq_residual(g, w, h, model, pm)[0]) / (2 * hstep)
+        scale = np.abs(Jfd).max()
+        assert np.abs(e["J"] - Jfd).max() < 1e-7 * scale
+        r, _ = _lstsq_residual(g, w, h, model, pt)
+        # normal matrix and right-hand side from the finite-difference Jacobian
+        np.testing.assert_allclose(e["A"], Jfd.T @ Jfd, rtol=1e-6, atol=1e-7 * scale ** 2)
+        np.testing.assert_allclose(e["b"], -Jfd.T @ r, rtol=1e-6,
+                                   atol=1e-7 * scale * np.abs(r).sum())
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_gradient_is_derivative_of_chi2(model):
+    """The right-hand side of Eq. 12 is -1/2 d chi^2/dp (a descent direction)."""
+    rng = np.random.default_rng(3)
+    for trial in range(10):
+        g, p = _rand_spot(rng, 13, 13, model)
+        pt = p + rng.normal(0, 0.2, size=p.shape)
+        e = oracle.eval_spot(g, 13, 13, model, pt, grad=True)
+        for j in range(len(pt)):
+            hstep = 1e-5
+            pp, pm = pt.copy(), pt.copy()
+            pp[j] += hstep
+            pm[j] -= hstep
+            cp = oracle.eval_spot(g, 13, 13, model, pp, grad=False)["chi2"]
+            cm = oracle.eval_spot(g, 13, 13, model, pm, grad=False)["chi2"]
+            d = (cp - cm) / (2 * hstep)
+            assert -2 * e["b"][j] == pytest.approx(d, rel=1e-6, abs=1e-6 * abs(cp))
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_envelope_identity(model):
+    """Sum r f = sum r = 0 at alpha_hat, beta_hat (Eq. 4), hence J^T r = alpha sum r df_j."""
+    rng = np.random.default_rng(4)
+    g, p = _rand_spot(rng, 15, 15, model)
+    pt = p + 0.1
+    e = oracle.eval_spot(g, 15, 15, model, pt, grad=True, want_J=True)
+    r, coef = _lstsq_residual(g, 15, 15, model, pt)
+    f = _profile_np(15, 15, model, pt)
+    assert abs(r @ f) < 1e-9 * np.abs(r).sum()
+    assert abs(r.sum()) < 1e-9 * np.abs(r).sum()
+    # alpha * df_j is the part of J_j not in span{f, 1}; project both and compare
+    Jr = e["J"].T @ r
+    np.testing.assert_allclose(-e["b"], Jr, rtol=1e-10, atol=1e-10 * np.abs(Jr).max())
+
+
+def test_symmetric_is_elliptical_with_equal_widths():
+    """The elliptical model at sigma_x = sigma_y reduces to Eq. 10; d/dsigma = d/dsx + d/dsy."""
+    rng = np.random.default_rng(5)
+    g, p = _rand_spot(rng, 11, 11, 0)
+    es = oracle.eval_spot(g, 11, 11, 0, p, grad=True, want_J=True)
+    ee = oracle.eval_spot(g, 11, 11, 1, [p[0], p[1], p[2], p[2]], grad=True, want_J=True)
+    for k in ("alpha", "beta", "chi2"):
+        assert es[k] == pytest.approx(ee[k], rel=1e-13)
+    np.testing.assert_allclose(es["J"][:, :2], ee["J"][:, :2], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(es["J"][:, 2], ee["J"][:, 2] + ee["J"][:, 3], rtol=1e-11,
+                               atol=1e-11)
+
+
+def test_damped_solve_matches_dense_solve():
+    """Eq. 14: (A + lambda diag A) delta = b; a singular matrix gives NaN."""
+    rng = np.random.default_rng(6)
+    for n in (3, 4):
+        for _ in range(20):
+            X = rng.normal(size=(10, n))
+            A = X.T @ X
+            b = rng.normal(size=n)
+            lam = 10.0 ** rng.integers(-8, 5)
+            d, rc = oracle.solve(A, b, lam)
+            ref = np.linalg.solve(A + lam * np.diag(np.diag(A)), b)
+            assert rc == 0
+            np.testing.assert_allclose(d, ref, rtol=1e-9, atol=1e-12)
+    d, rc = oracle.solve(np.zeros((3, 3)), np.ones(3), 0.01)
+    assert rc == 1 and np.all(np.isnan(d))
+
+
+def test_pow10_is_correctly_rounded():
+    for k in range(-22, 23):
+        assert oracle.pow10(k) == float(f"1e{k}")
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_noise_free_recovery(model):
+    """Exact float64 renders are fitted back to the true parameters to 1e-9."""
+    rng = np.random.default_rng(7)
+    o = oracle.default_opts(max_error_per_px=0.0, max_iter=60, min_delta=0.0,
+                            min_step_rel=0.0)
+    for trial in range(20):
+        w = h = [9, 11, 15, 21][trial % 4]
+        n = 3 if model == 0 else 4
+        truth = np.array([(w - 1) / 2 + rng.uniform(-1, 1), (h - 1) / 2 + rng.uniform(-1, 1),
+                          rng.uniform(1.2, 2.5), rng.uniform(1.2, 2.5)])[:n]
+        a, b = rng.uniform(200, 3000), rng.uniform(10, 300)
+        g = a * _profile_np(w, h, model, truth) + b
+        init = np.array([truth[0] + 0.4, truth[1] - 0.3, truth[2] * 1.2,
+                         truth[-1] * 0.85], dtype=np.float32)
+        r = oracle.fit_spot(g, w, h, model, init, o)
+        got = r["params"][[0, 1, 2, 3]][:n] if model == 1 else r["params"][:3]
+        assert np.abs(got - truth).max() < 1e-9, (r, truth)
+        assert r["params"][4] == pytest.approx(a, rel=1e-9)
+        assert r["params"][5] == pytest.approx(b, rel=1e-9, abs=1e-7)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_equals_explicit_five_parameter_fit(model):
+    """Implicit amplitudes reach the minimum of the full objective of Eq. 1 (scipy LM)."""
+    rng = np.random.default_rng(8)
+    o = oracle.default_opts(max_error_per_px=0.0, max_iter=200, min_delta=0.0,
+                            min_step_rel=1e-13)
+    for trial in range(12):
+        w = h = [9, 11, 15][trial % 3]
+        g, p = _rand_spot(rng, w, h, model)
+        init = np.concatenate([p, p[-1:]]) if model == 0 else p
+        init = (init + rng.normal(0, 0.2, 4)).astype(np.float32)
+        init[2:] = np.abs(init[2:]) + 0.3
+        r = oracle.fit_spot(g, w, h, model, init, o)
+        n = 3 if model == 0 else 4
+        q0 = np.concatenate([r["params"][:n] + 0.05, [r["params"][4] * 1.1, r["params"][5] - 3]])
+
+        def res(q):
+            return q[n] * _profile_np(w, h, model, q[:n]) + q[n + 1] - g
+
+        sol = scipy.optimize.least_squares(res, q0, method="lm", xtol=1e-15, ftol=1e-15,
+                                           gtol=1e-15, max_nfev=20000)
+        ref = np.concatenate([sol.x[:n], sol.x[n:]])
+        got = np.concatenate([r["params"][:n], r["params"][4:6]])
+        np.testing.assert_allclose(got, ref, rtol=1e-7, atol=1e-7)
+        assert r["chi2"] == pytest.approx(float(sol.fun @ sol.fun), rel=1e-10)
+
+
+def _grid_chi2(g, w, h, xs, ys, ss):
+    """chi^2 minimised over (alpha, beta) at every (x, y, sigma) grid point."""
+    px, py = _grid_xy(w, h)
+    X, Y, S = np.meshgrid(xs, ys, ss, indexing="ij")
+    X, Y, S = X.ravel(), Y.ravel(), S.ravel()
+    best = np.full(X.shape, np.inf)
+    N = w * h
+    G, G2 = g.sum(), (g * g).sum()
+    for c0 in range(0, X.size, 200000):
+        sl = slice(c0, c0 + 200000)
+        f = np.exp(-((px[None] - X[sl, None]) ** 2 + (py[None] - Y[sl, None]) ** 2) /
+                   (2 * S[sl, None] ** 2))
+        F, FF, FG = f.sum(1), (f * f).sum(1), f @ g
+        # 2x2 normal equations solved with numpy per point, residual computed directly
+        M = np.stack([np.stack([FF, F], -1), np.stack([F, np.full_like(F, N)], -1)], -2)
+        rhs = np.stack([FG, np.full_like(F, G)], -1)
+        coef = np.linalg.solve(M, rhs[..., None])[..., 0]
+        r = coef[:, :1] * f + coef[:, 1:] - g[None]
+        best[sl] = (r * r).sum(1)
+    i = int(np.argmin(best))
+    return best[i], (X[i], Y[i], S[i])
+
+
+@pytest.mark.parametrize("side", [5, 7])
+def test_global_minimum_by_grid_search(side):
+    """On tiny spots the fitted chi^2 is the global minimum found by brute force."""
+    rng = np.random.default_rng(9 + side)
+    for trial in range(3):
+        g, p = _rand_spot(rng, side, side, 0)
+        init = np.array([p[0] + 0.3, p[1] - 0.2, p[2] * 1.15, 0], dtype=np.float32)
+        r = oracle.fit_spot(g, side, side, 0, init,
+                            oracle.default_opts(max_error_per_px=0.0, max_iter=100,
+                                                min_delta=1e-14, min_step_rel=1e-12))
+        # coarse grid over the whole box, then a fine grid (step 0.005) around its best
+        c2, (cx, cy, cs) = _grid_chi2(g, side, side, np.arange(-0.5, side - 0.5, 0.05),
+                                      np.arange(-0.5, side - 0.5, 0.05),
+                                      np.arange(0.5, 4.0, 0.05))
+        step = 0.005
+        f2, (fx, fy, fs) = _grid_chi2(g, side, side, np.arange(cx - 0.1, cx + 0.1 + 1e-9, step),
+                                      np.arange(cy - 0.1, cy + 0.1 + 1e-9, step),
+                                      np.arange(cs - 0.1, cs + 0.1 + 1e-9, step))
+        assert r["chi2"] <= f2 * (1 + 1e-12)
+        assert abs(r["params"][0] - fx) <= step and abs(r["params"][1] - fy) <= step
+        assert abs(r["params"][2] - fs) <= step
+
+
+def test_degenerate_and_bad_inputs():
+    o = oracle.default_opts()
+    # constant spot: alpha = 0, chi^2 = 0 < N/3 -> MaxError at the first iteration
+    r = oracle.fit_spot(np.full(81, 100.0), 9, 9, 0, [4, 4, 1.5, 1.5], o)
+    assert r["status"] == oracle.MAX_ERROR and r["iters"] == 1 and r["chi2"] < 1e-18
+    # NaN pixel -> NaN error -> NotConverged at the first iteration
+    g = np.full(81, 100.0)
+    g[5] = np.nan
+    r = oracle.fit_spot(g, 9, 9, 0, [4, 4, 1.5, 1.5], o)
+    assert r["status"] == oracle.NOT_CONVERGED and r["iters"] == 1
+    # spot-level input errors
+    for (w, h, model, init) in [(2, 9, 0, [1, 4, 1, 1]), (33, 32, 0, [4, 4, 1, 1]),
+                                (9, 9, 7, [4, 4, 1, 1]), (9, 9, 0, [np.nan, 4, 1, 1]),
+                                (9, 9, 0, [4, 4, 0.0, 1]), (9, 9, 1, [4, 4, 1.0, -1])]:
+        g = np.full(w * h, 10.0)
+        r = oracle.fit_spot(g, w, h, model, init, o)
+        assert r["status"] == oracle.BAD_INPUT and r["iters"] == 0
+        assert np.all(np.isnan(r["params"]))
+    # a zero iteration budget returns the init with status MaxIter
+    o0 = oracle.default_opts(max_iter=0)
+    b = spotgen.config(0, n=4)
+    r = oracle.fit_spot(b.spot(0).astype(float), 11, 11, 0, b.init[0], o0)
+    assert r["status"] == oracle.MAX_ITER and r["iters"] == 0
+    assert r["params"][0] == pytest.approx(float(b.init[0, 0]))
+
+
+def test_batch_driver_matches_single_spots_and_threads():
+    b = spotgen.config(3, n=300)
+    r1 = oracle.fit_batch(b, threads=1)
+    r4 = oracle.fit_batch(b, threads=4)
+    for k in r1:
+        np.testing.assert_array_equal(r1[k], r4[k])
+    for s in range(0, 300, 37):
+        w, h, m = (int(v) for v in b.sizes[s, :3])
+        rs = oracle.fit_spot(b.spot(s).astype(float), w, h, m, b.init[s])
+        np.testing.assert_array_equal(rs["params"], r1["params"][s])
+        assert rs["status"] == r1["status"][s] and rs["iters"] == r1["iters"][s]
+
+
+def test_table1_accuracy_statistics():
+    """Table 1 (Fit2DGaussian rows) with the paper's protocol and initial values."""
+    with open(os.path.join(GOLDEN, "table1_accuracy.json")) as fh:
+        gold = json.load(fh)
+    for row in gold["rows"]:
+        b = spotgen.paper_protocol(20000, 9, row["n_signal"], row["n_background"], seed=17)
+        r = oracle.fit_batch(b, threads=8)
+        st = b.truth
+        exy = np.concatenate([np.abs(r["params"][:, 0] - st[:, 0]),
+                              np.abs(r["params"][:, 1] - st[:, 1])]) / np.tile(st[:, 2], 2)
+        es = np.abs(np.abs(r["params"][:, 2]) - st[:, 2]) / st[:, 2]
+        got_xy = [np.median(exy), exy.mean(), exy.std()]
+        got_s = [np.median(es), es.mean(), es.std()]
+        np.testing.assert_allclose(got_xy, row["xy"], rtol=0.06)
+        np.testing.assert_allclose(got_s, row["sigma"], rtol=0.08)
+
+
+def test_fig8_iteration_and_stop_statistics():
+    """1600:40 counts: typically 4-5 iterations, MinDelta dominates, almost none exhausted."""
+    with open(os.path.join(GOLDEN, "iterations_fig8.json")) as fh:
+        gold = json.load(fh)["statements"]
+    b = spotgen.paper_protocol(20000, 9, 1600, 40, seed=18)
+    r = oracle.fit_batch(b, threads=8)
+    hist = np.bincount(r["iters"], minlength=21) / b.n
+    lo, hi = gold["typical_iterations"]
+    assert hist[lo] + hist[hi] > 0.8
+    assert int(np.argmax(hist)) in (lo, hi)
+    st = np.bincount(r["status"], minlength=6) / b.n
+    assert st[oracle.MIN_DELTA] > 0.5
+    assert st[oracle.MAX_ITER] < 0.005
+    # double precision keeps MinStep rare, though above the paper's single-precision < 1 %
+    assert st[oracle.MIN_STEP] < 0.1
