@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the batched Gaussian-spot fit on one MI355X.
+
+One step = one call of spotfit_fit_spots over the whole workload (every spot
+fitted to completion), inputs resident in HBM.  Default workload: 1,000,000
+spots of 15x15 uint16 pixels, symmetric Gaussian, sigma U[1,3], amplitude
+log-uniform [1e2, 1e4], background U[10, 200], Poisson plus read noise (sd 2).
+
+Prints one JSON line: fits/s (whole job), the fit kernel's roofline figures
+measured live with HIP events on the launch stream, and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak of this chip for single-lane FP32 / FP64 FMA: 256 CUs x 4 SIMD x 16 lanes
+# x 2 flop x 2.4 GHz.  (The 157.3 TFLOP/s FP32 figure needs packed FP32
+# instructions, which this build does not emit.)
+PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_HBM_GBPS = 8000.0
+
+# Algorithmic work per spot of N pixels with n_g derivative and n_t trial
+# evaluations: N * (C_g n_g + C_t n_t - 11 (n_g - 1)) flop, exp count N (n_t + 1).
+C_GRAD = {0: 66, 1: 88}
+C_TRIAL = 16
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="scale_15x15")
+    ap.add_argument("--n", type=int, default=None, help="spots (default: the workload's size)")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32"])
+    ap.add_argument("--tie-tau", type=float, default=0.0)
+    ap.add_argument("--cpu-sample", type=int, default=1000000,
+                    help="spots of the same workload fitted by the CPU oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {a.gpus}); the fit shards by "
+              "independent spots, so N GPUs would each run this same benchmark on 1/N of "
+              "the spots.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2106_02045_amd as sf
+    import spotgen
+
+    t0 = time.time()
+    batch = spotgen.workload(a.workload, n=a.n, threads=16)
+    gen_s = time.time() - t0
+    n = batch.n
+    npix = batch.npix()
+    max_px = int(npix.max())
+    dev = torch.device("cuda:0")
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    data, sizes, offs, init = up(batch.data), up(batch.sizes), up(batch.offsets), up(batch.init)
+    ctx = sf.Context(0)
+    prec = sf.PREC_MIXED if a.precision == "mixed" else sf.PREC_FP32
+    opts = sf.default_options(precision=prec, max_pixels=max(9, max_px), tie_tau=a.tie_tau)
+    out = ctx.fit_spots(data, sizes, offs, init, opts, want_evals=True)
+    torch.cuda.synchronize()
+
+    # algorithmic work from the evaluation counts (the fit is deterministic, so the
+    # timed launches below do exactly this work)
+    ev = out["evals"].cpu().numpy().astype(np.int64)
+    models = batch.sizes[:, 2].astype(np.int64)
+    cg = np.where(models == 1, C_GRAD[1], C_GRAD[0])
+    ng, nt = ev[:, 0], ev[:, 1]
+    flops = float((npix * (cg * ng + C_TRIAL * nt - 11 * np.maximum(ng - 1, 0))).sum())
+    exps = float((npix * (nt + 1)).sum())
+    bytes_in = float(batch.data.nbytes + batch.sizes.nbytes + batch.offsets.nbytes +
+                     batch.init.nbytes)
+    bytes_out = float(n * (6 * 4 + 4 + 4 + 4))
+    alg_bytes = bytes_in + bytes_out
+    status = out["status"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    del out["evals"]
+
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(a.warmup):
+        ctx.fit_spots(data, sizes, offs, init, opts, out=out, stream=stream)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(a.steps):
+        starts[i].record(stream)
+        ctx.fit_spots(data, sizes, offs, init, opts, out=out, stream=stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    kms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    k_avg_s = sum(kms) / len(kms) / 1e3
+    ms_per_step = wall / a.steps * 1e3
+    fits_per_s = n / (wall / a.steps)
+
+    achieved_tflops = flops / k_avg_s / 1e12
+    hbm_gbps = alg_bytes / k_avg_s / 1e9
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        m = min(a.cpu_sample, n)
+        sub = spotgen.workload(a.workload, n=m)
+        threads = min(os.cpu_count() or 1, 16)
+        oo = oracle.default_opts(tie_tau=a.tie_tau)
+        c0 = time.perf_counter()
+        oracle.fit_batch(sub, oo, threads=threads)
+        cs = time.perf_counter() - c0
+        cpu = {"value": m / cs, "unit": "fits/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {m} spots of {a.workload} (same generator and seed), "
+                         f"{cs:.2f} s wall on {threads} threads"}
+
+    rec = {
+        "metric": "fits/s",
+        "value": fits_per_s,
+        "unit": "fits/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == sf.PREC_MIXED else "f32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "spots": n, "roi": f"{batch.sizes[0,0]}x{batch.sizes[0,1]}"
+                   if len(np.unique(npix)) == 1 else "mixed", "pixel_dtype": "u16",
+                   "precision": a.precision, "tie_tau": a.tie_tau},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_ALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_ALU_TFLOPS,
+                     "traffic": None},
+        "hbm": {"achieved_algorithmic_GBps": hbm_gbps, "peak_GBps": PEAK_HBM_GBPS,
+                "frac": hbm_gbps / PEAK_HBM_GBPS, "bytes_per_launch": alg_bytes},
+        "kernel_ms_avg": k_avg_s * 1e3,
+        "exp_per_s": exps / k_avg_s,
+        "evals_per_spot": {"grad": float(ng.mean()), "trial": float(nt.mean())},
+        "status_hist": np.bincount(status, minlength=6).tolist(),
+        "iters_mean": float(iters.mean()),
+        "cpu_baseline": cpu,
+        "gen_s": gen_s,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,147 @@
+/*
+ * spotfit.h -- C ABI of the MI355X (gfx950) batched Gaussian-spot fitter.
+ *
+ * Fits many small image spots (at most 1024 pixels each) to a 2D Gaussian with
+ * implicit amplitudes by damped Levenberg-Marquardt, as described by
+ * Leutenegger & Weber, "Least-squares fitting of Gaussian spots on graphics
+ * processing units":
+ *   model      h_i = alpha_hat(p) f_i(p) + beta_hat(p) (Eqs. 2-3); only the
+ *              shaping parameters p are iterated
+ *   amplitudes closed form of the 2x2 normal equations (Eqs. 5-6)
+ *   derivatives of the amplitudes and the residuals (Eqs. 7-9)
+ *   profiles   symmetric Gaussian p = (x, y, sigma) (Eqs. 10-11), or
+ *              axis-aligned elliptical p = (x, y, sigma_x, sigma_y)
+ *   step       (J^T J + lambda diag J^T J) delta = J^T (g - h) (Eqs. 12, 14),
+ *              lambda from 0.01, /10 after an improvement, x10 per retry up to
+ *              1e4 (Levenberg-Marquardt section); stop rules of the
+ *              Fit2DGaussian pseudo-code with the Results-section thresholds.
+ *
+ * Everything runs on the GPU; this header names no HIP or torch type.  A
+ * stream argument is a hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Pixel data layout (all device memory, caller-owned):
+ *   data    uint16 or float32 values; spot s occupies elements
+ *           [offsets[s], offsets[s] + w*h), row-major: pixel k = row*w + col
+ *           lies at x = col, y = row (0-based pixel centres)
+ *   sizes   spotfit_shape_t[n] (w, h, model)
+ *   init    float[n][4] = (x, y, sigma_x, sigma_y); symmetric spots read sigma_x
+ * Outputs (device, caller-owned, must not alias inputs):
+ *   params_out float[n][6] = (x, y, sigma_x, sigma_y, alpha_hat, beta_hat);
+ *              symmetric spots report sigma_y = sigma_x
+ *   chi2_out   float[n]  raw sum of squared residuals at params_out (the
+ *              paper's "normalized" chi^2 is left to the caller, e.g.
+ *              chi2 / (w*h - n_params - 2))
+ *   iters_out  int32[n]  LM iterations started
+ *   status_out int32[n]  spotfit_status_t
+ *   evals_out  int32[n][2] or NULL: (derivative evaluations, trial evaluations)
+ *
+ * Error behaviour: a call returns SPOTFIT_OK or a negative spotfit_error_t.
+ * Call-level problems (NULL handle or array, n < 0, invalid options) are
+ * detected on the host before any HIP call; n == 0 is a no-op.  Spot-level
+ * problems never fail the call: a spot with w or h < 3, w*h above the
+ * capacity (1024, or opt.max_pixels when smaller), an unknown model, a
+ * non-finite start value or a start width <= 0 gets status SPOTFIT_BAD_INPUT,
+ * NaN params and chi^2, and 0 iterations.
+ *
+ * Asynchrony: work is enqueued on the stream and the call returns; results
+ * are valid after the stream is synchronised.  Calls on one context are not
+ * thread-safe against each other.
+ */
+#ifndef SPOTFIT_H
+#define SPOTFIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spotfit_ctx spotfit_ctx_t; /* opaque: device properties, kernel plans */
+
+typedef enum { SPOTFIT_U16 = 0, SPOTFIT_F32 = 1 } spotfit_dtype_t;
+typedef enum { SPOTFIT_SYM = 0, SPOTFIT_ELL = 1 } spotfit_model_t;
+
+/* Per-spot stop condition (Fit2DGaussian pseudo-code; the paper leaves the codes unnamed). */
+typedef enum {
+  SPOTFIT_MAX_ITER = 0,      /* iteration budget used up after an accepted step          */
+  SPOTFIT_MAX_ERROR = 1,     /* chi^2 below max_error_per_px * w*h                       */
+  SPOTFIT_MIN_DELTA = 2,     /* chi*(1 - min_delta) < Chi: too small an improvement      */
+  SPOTFIT_MIN_STEP = 3,      /* every |delta_j| < min_step_rel * |p_j|                   */
+  SPOTFIT_NOT_CONVERGED = 4, /* NaN error, or no decrease after the damping retries;
+                                the parameters before the failed step are returned    */
+  SPOTFIT_BAD_INPUT = 5      /* spot-level input error, see above                       */
+} spotfit_status_t;
+
+/* Arithmetic of the fit kernel. */
+typedef enum {
+  SPOTFIT_PREC_FP32 = 0,  /* plain single precision everywhere, the paper's arithmetic    */
+  SPOTFIT_PREC_MIXED = 1  /* default: FP32 profile and derivative sums, double-precision
+                             parameters, amplitude determinant, residual, chi^2
+                             accumulation and LM solve                                  */
+} spotfit_precision_t;
+
+typedef enum {
+  SPOTFIT_OK = 0,
+  SPOTFIT_E_NULL = -1,     /* NULL context, output or input array with n > 0           */
+  SPOTFIT_E_ARG = -2,      /* n < 0, unknown dtype                                       */
+  SPOTFIT_E_OPTIONS = -3,  /* options out of range                                       */
+  SPOTFIT_E_HIP = -4,      /* a HIP runtime call failed (message via spotfit_last_error) */
+  SPOTFIT_E_DEVICE = -5    /* no usable gfx950 device                                    */
+} spotfit_error_t;
+
+typedef struct {
+  uint8_t w, h;      /* ROI width (columns) and height (rows), 3..32 each, w*h <= 1024 */
+  uint8_t model;     /* spotfit_model_t                                                */
+  uint8_t reserved;  /* 0                                                              */
+} spotfit_shape_t;
+
+typedef struct {
+  int32_t max_iter;         /* iteration budget, >= 0 (paper: 20)                          */
+  int32_t lambda0_exp10;    /* initial damping 10^k0 (paper: 0.01 -> -2)                   */
+  int32_t lambda_max_exp10; /* retry while k < this (paper: 1e4 -> 4)                      */
+  int32_t precision;        /* spotfit_precision_t                                          */
+  double max_error_per_px;  /* MaxError iff chi^2 < this * w*h (paper "A/3" -> 1/3)        */
+  double min_delta;         /* MinDelta iff chi*(1 - min_delta) < Chi (paper: 1e-6)         */
+  double min_step_rel;      /* MinStep iff all |delta_j| < this * |p_j| (paper: 1e-4)       */
+  double tie_tau;           /* chi^2 changes within +-tie_tau*chi count as ties: neither
+                               "improved" nor "worse"; 0 = the paper's exact comparisons  */
+  double sigma_min;         /* parameter box of limit(): sigma >= sigma_min (0.3)          */
+  double sigma_max_frac;    /* ... sigma <= sigma_max_frac * max(w, h) (1.0); x in
+                               [-0.5, w-0.5], y in [-0.5, h-0.5]                           */
+  int32_t max_pixels;       /* capacity promise: spots with w*h > max_pixels are
+                               BAD_INPUT; smaller values select leaner kernels (1024)     */
+  int32_t reserved;
+} spotfit_options_t;
+
+/* Fill *opt with the paper's settings (Results section) and the defaults above. */
+void spotfit_default_options(spotfit_options_t* opt);
+
+/* SPOTFIT_OK if the options are usable, SPOTFIT_E_OPTIONS otherwise.  Host only. */
+int spotfit_validate_options(const spotfit_options_t* opt);
+
+/* Create a context on HIP device `device` (makes it current).  *ctx is owned by
+ * the caller and released with spotfit_ctx_destroy.  Returns SPOTFIT_E_DEVICE if
+ * the device is not gfx950. */
+int spotfit_ctx_create(spotfit_ctx_t** ctx, int device);
+void spotfit_ctx_destroy(spotfit_ctx_t* ctx);
+
+/* Fit n_spots spots (see the layout above) on `stream`.  All array arguments
+ * are device pointers; opt is a host pointer (NULL = defaults).  Allocates
+ * nothing.  Returns SPOTFIT_OK or a negative spotfit_error_t. */
+int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                      const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
+                      int64_t n_spots, const spotfit_options_t* opt, float* params_out,
+                      float* chi2_out, int32_t* iters_out, int32_t* status_out,
+                      int32_t* evals_out, void* stream);
+
+/* Text of the last error on this thread ("" if none).  Host only. */
+const char* spotfit_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int spotfit_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPOTFIT_H */

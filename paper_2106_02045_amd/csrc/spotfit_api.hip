@@ -1,0 +1,186 @@
+// spotfit_api.hip -- host side of the C ABI declared in include/spotfit.h:
+// option defaults and validation, the device context and the launch of the fit
+// kernels.  Every check runs on the host before any HIP call; the fit itself
+// runs entirely on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "spotfit.h"
+#include "spotfit_internal.h"
+
+struct spotfit_ctx {
+  int device;
+  int n_cu;
+  // resident 64-lane workgroups per CU, per (ppl class, precision)
+  int occupancy[5][2];
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* what) {
+  g_last_error = what;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+  return SPOTFIT_E_HIP;
+}
+
+int ppl_index(int ppl) {
+  switch (ppl) {
+    case 1: return 0;
+    case 2: return 1;
+    case 4: return 2;
+    case 8: return 3;
+    default: return 4;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void spotfit_default_options(spotfit_options_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->max_iter = 20;               // Results section: at most 20 iterations
+  o->lambda0_exp10 = -2;          // LM section: initial damping 0.01
+  o->lambda_max_exp10 = 4;        // LM section: stop once damping would exceed 1e4
+  o->precision = SPOTFIT_PREC_MIXED;
+  o->max_error_per_px = 1.0 / 3.0;  // Results section: chi^2 < A/3, A = pixel count
+  o->min_delta = 1e-6;            // Results section: decrease below 1e-6 chi^2
+  o->min_step_rel = 1e-4;         // Results section: |dp_j| < 1e-4 |p_j|
+  o->tie_tau = 0.0;
+  o->sigma_min = 0.3;
+  o->sigma_max_frac = 1.0;
+  o->max_pixels = 1024;           // Implementation section: at most 1024 pixels per fit
+}
+
+int spotfit_validate_options(const spotfit_options_t* o) {
+  if (!o) return fail(SPOTFIT_E_NULL, "options: NULL");
+  if (o->max_iter < 0 || o->max_iter > 1000) return fail(SPOTFIT_E_OPTIONS, "max_iter not in [0, 1000]");
+  if (o->lambda0_exp10 < -300 || o->lambda0_exp10 > 300 || o->lambda_max_exp10 < -300 ||
+      o->lambda_max_exp10 > 300)
+    return fail(SPOTFIT_E_OPTIONS, "lambda exponents not in [-300, 300]");
+  if (o->precision != SPOTFIT_PREC_FP32 && o->precision != SPOTFIT_PREC_MIXED)
+    return fail(SPOTFIT_E_OPTIONS, "unknown precision");
+  if (!std::isfinite(o->max_error_per_px) || o->max_error_per_px < 0)
+    return fail(SPOTFIT_E_OPTIONS, "max_error_per_px must be finite and >= 0");
+  if (!std::isfinite(o->min_delta) || o->min_delta < 0 || o->min_delta >= 1)
+    return fail(SPOTFIT_E_OPTIONS, "min_delta not in [0, 1)");
+  if (!std::isfinite(o->min_step_rel) || o->min_step_rel < 0)
+    return fail(SPOTFIT_E_OPTIONS, "min_step_rel must be finite and >= 0");
+  if (!std::isfinite(o->tie_tau) || o->tie_tau < 0 || o->tie_tau >= 1)
+    return fail(SPOTFIT_E_OPTIONS, "tie_tau not in [0, 1)");
+  if (!std::isfinite(o->sigma_min) || o->sigma_min <= 0)
+    return fail(SPOTFIT_E_OPTIONS, "sigma_min must be > 0");
+  if (!std::isfinite(o->sigma_max_frac) || o->sigma_max_frac * 3.0 <= o->sigma_min)
+    return fail(SPOTFIT_E_OPTIONS, "sigma_max_frac * 3 must exceed sigma_min");
+  if (o->max_pixels < 9 || o->max_pixels > 1024)
+    return fail(SPOTFIT_E_OPTIONS, "max_pixels not in [9, 1024]");
+  return SPOTFIT_OK;
+}
+
+int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
+  if (!out) return fail(SPOTFIT_E_NULL, "ctx_create: NULL out pointer");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(SPOTFIT_E_DEVICE, "ctx_create: no such device");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SPOTFIT_E_DEVICE, "ctx_create: device is not gfx950");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+  spotfit_ctx* c = new (std::nothrow) spotfit_ctx();
+  if (!c) return fail(SPOTFIT_E_DEVICE, "ctx_create: out of host memory");
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  const int ppls[5] = {1, 2, 4, 8, 16};
+  for (int i = 0; i < 5; ++i) {
+    for (int pr = 0; pr < 2; ++pr) {
+      int nb = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sf::wave_kernel_symbol(ppls[i], pr), 64, 0);
+      if (e != hipSuccess) {
+        delete c;
+        return fail_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+      }
+      c->occupancy[i][pr] = nb > 0 ? nb : 1;
+    }
+  }
+  *out = c;
+  return SPOTFIT_OK;
+}
+
+void spotfit_ctx_destroy(spotfit_ctx_t* ctx) { delete ctx; }
+
+int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                      const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
+                      int64_t n, const spotfit_options_t* opt, float* params_out,
+                      float* chi2_out, int32_t* iters_out, int32_t* status_out,
+                      int32_t* evals_out, void* stream) {
+  if (!ctx) return fail(SPOTFIT_E_NULL, "fit_spots: NULL context");
+  if (n < 0) return fail(SPOTFIT_E_ARG, "fit_spots: n_spots < 0");
+  if (dtype != SPOTFIT_U16 && dtype != SPOTFIT_F32) return fail(SPOTFIT_E_ARG, "fit_spots: unknown dtype");
+  spotfit_options_t o;
+  if (opt) {
+    o = *opt;
+  } else {
+    spotfit_default_options(&o);
+  }
+  int rc = spotfit_validate_options(&o);
+  if (rc != SPOTFIT_OK) return rc;
+  if (n == 0) return SPOTFIT_OK;
+  if (!data || !sizes || !offsets || !init || !params_out || !chi2_out || !iters_out || !status_out)
+    return fail(SPOTFIT_E_NULL, "fit_spots: NULL array");
+
+  sf::KArgs ka;
+  std::memset(&ka, 0, sizeof ka);
+  ka.data = data;
+  ka.sizes = sizes;
+  ka.offsets = offsets;
+  ka.init = init;
+  ka.params_out = params_out;
+  ka.chi2_out = chi2_out;
+  ka.iters_out = iters_out;
+  ka.status_out = status_out;
+  ka.evals_out = evals_out;
+  ka.n = n;
+  ka.dtype = dtype;
+  ka.opt.max_iter = o.max_iter;
+  ka.opt.lambda0_exp10 = o.lambda0_exp10;
+  ka.opt.lambda_max_exp10 = o.lambda_max_exp10;
+  ka.opt.max_pixels = o.max_pixels;
+  ka.opt.max_error_per_px = o.max_error_per_px;
+  ka.opt.min_delta = o.min_delta;
+  ka.opt.min_step_rel = o.min_step_rel;
+  ka.opt.tie_tau = o.tie_tau;
+  ka.opt.sigma_min = o.sigma_min;
+  ka.opt.sigma_max_frac = o.sigma_max_frac;
+
+  const int ppl = sf::ppl_for_pixels(o.max_pixels);
+  const int pr = o.precision == SPOTFIT_PREC_MIXED ? 1 : 0;
+  // persistent grid: as many one-wave workgroups as can be resident at once
+  const int64_t resident = (int64_t)ctx->n_cu * ctx->occupancy[ppl_index(ppl)][pr];
+  const int grid = (int)(n < resident ? n : resident);
+  hipError_t e = sf::launch_wave_kernel(ppl, o.precision, ka, grid, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "fit kernel launch");
+  return SPOTFIT_OK;
+}
+
+const char* spotfit_last_error(void) { return g_last_error.c_str(); }
+
+int spotfit_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+"""Comparison of GPU fit results with the double-precision oracle.
+
+Tolerances (per spot): |dx|, |dy| < 1e-3 px; relative sigma, alpha, beta < 1e-4;
+relative chi^2 < 1e-5; identical status and iteration count.  A spot whose
+oracle trajectory passes a decision closer than the kernel's chi^2 error to its
+threshold ("knife-edge": the oracle logs the smallest relative margin of every
+chi^2 comparison and every step-size comparison it makes) may legitimately take
+the other branch; such spots are counted and reported, and must still satisfy
+the parameter tolerances when they end with the same status.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+TOL_XY = 1e-3
+TOL_REL = 1e-4
+TOL_CHI = 1e-5
+
+
+def _rel(a, b):
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.abs(a / b - 1.0)
+
+
+def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None) -> dict:
+    """g: GPU outputs (params [n,6] f32, chi2, iters, status); r: oracle.fit_batch dict."""
+    gp = np.asarray(g["params"], dtype=np.float64)
+    rp = r["params"]
+    n = len(rp)
+    bad_in = r["status"] == 5
+    dxy = np.abs(gp[:, :2] - rp[:, :2]).max(1)
+    rel = _rel(gp[:, 2:6], rp[:, 2:6])
+    # beta can be ~0 on low-background spots: compare it relative to the spot's level
+    scale_b = np.maximum(np.abs(rp[:, 5]), 1e-3 * np.abs(rp[:, 4]))
+    rel[:, 3] = np.abs(gp[:, 5] - rp[:, 5]) / scale_b
+    relmax = rel.max(1)
+    rchi = _rel(np.asarray(g["chi2"], np.float64), r["chi2"])
+    rchi = np.where((r["chi2"] == 0) & (np.asarray(g["chi2"]) == 0), 0.0, rchi)
+    same_status = g["status"] == r["status"]
+    same_iters = g["iters"] == r["iters"]
+    knife = (r["margin_chi"] < chi_band) | (r["margin_step"] < step_band)
+    in_tol = (dxy < TOL_XY) & (relmax < TOL_REL) & (rchi < TOL_CHI)
+    in_tol = np.where(bad_in, True, in_tol)
+    # BAD_INPUT: status must match and outputs must be NaN on both sides
+    nan_ok = np.all(np.isnan(gp[bad_in]))
+    same = same_status & same_iters
+    strict = ~knife
+    return dict(
+        n=n,
+        n_knife=int(knife.sum()),
+        status_mismatch=int((~same_status).sum()),
+        iters_mismatch=int((~same_iters).sum()),
+        strict_mismatch=int((strict & ~same).sum()),
+        tol_fail_same=int((same & ~in_tol).sum()),
+        tol_fail_any=int((~in_tol).sum()),
+        max_dxy=float(np.nanmax(np.where(bad_in, 0, dxy))) if n else 0.0,
+        max_rel=float(np.nanmax(np.where(bad_in, 0, relmax))) if n else 0.0,
+        max_rchi=float(np.nanmax(np.where(bad_in, 0, rchi))) if n else 0.0,
+        med_rchi=float(np.nanmedian(rchi[~bad_in])) if (~bad_in).any() else 0.0,
+        bad_input_nan=bool(nan_ok),
+        mismatch_idx=np.nonzero(~same)[0],
+    )
+
+
+def summary(name: str, c: dict) -> str:
+    return (f"{name}: n={c['n']} knife={c['n_knife']} status_mis={c['status_mismatch']} "
+            f"iters_mis={c['iters_mismatch']} strict_mis={c['strict_mismatch']} "
+            f"tol_fail(same)={c['tol_fail_same']} tol_fail(any)={c['tol_fail_any']} "
+            f"max|dxy|={c['max_dxy']:.2e} max_rel={c['max_rel']:.2e} "
+            f"max_rchi={c['max_rchi']:.2e} med_rchi={c['med_rchi']:.2e}")

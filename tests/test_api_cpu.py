@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI: the library loads, exports what include/spotfit.h
+declares, and rejects bad calls on the host before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2106_02045_amd as sf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "spotfit.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spotfit_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported():
+    declared = _declared_functions()
+    assert declared, "no declarations found"
+    L = sf.lib()
+    for name in declared:
+        assert hasattr(L, name), f"{name} declared in spotfit.h but not exported"
+    assert sorted(sf.EXPORTED) == declared
+
+
+def test_header_compiles_as_c99(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "spotfit.h"\nint main(void){spotfit_options_t o; (void)o; return 0;}\n')
+    import subprocess
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-c",
+                        "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                        str(tmp_path / "t.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_options_struct_layout_matches_header():
+    # offsets of the C struct, checked by compiling a probe against the header
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "p.c")
+        fields = [f for f, _ in sf.Options._fields_]
+        body = "".join(f'printf("%zu ", offsetof(spotfit_options_t, {f}));' for f in fields)
+        with open(src, "w") as fh:
+            fh.write('#include <stdio.h>\n#include <stddef.h>\n#include "spotfit.h"\n'
+                     f'int main(void){{{body} printf("%zu", sizeof(spotfit_options_t)); return 0;}}\n')
+        exe = os.path.join(d, "p")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    offs = [getattr(sf.Options, f).offset for f in fields]
+    assert [int(v) for v in out[:-1]] == offs
+    assert int(out[-1]) == ctypes.sizeof(sf.Options)
+
+
+def test_default_options_are_the_papers():
+    o = sf.default_options()
+    assert o.max_iter == 20 and o.lambda0_exp10 == -2 and o.lambda_max_exp10 == 4
+    assert o.min_delta == 1e-6 and o.min_step_rel == 1e-4
+    assert o.max_error_per_px == pytest.approx(1 / 3)
+    assert o.max_pixels == 1024 and o.precision == sf.PREC_MIXED
+    assert sf.lib().spotfit_validate_options(ctypes.byref(o)) == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("max_iter", -1), ("max_iter", 5000), ("precision", 7), ("min_delta", 1.0),
+    ("min_delta", -1e-3), ("tie_tau", 1.5), ("sigma_min", 0.0), ("max_pixels", 2000),
+    ("max_pixels", 4), ("max_error_per_px", float("nan")), ("sigma_max_frac", 0.05),
+])
+def test_bad_options_rejected(field, value):
+    o = sf.default_options()
+    setattr(o, field, value)
+    assert sf.lib().spotfit_validate_options(ctypes.byref(o)) == -3
+    assert sf.lib().spotfit_last_error()
+
+
+def test_call_level_errors_before_any_gpu_call():
+    L = sf.lib()
+    o = sf.default_options()
+    # NULL context
+    rc = L.spotfit_fit_spots(None, 1, 0, 1, 1, 1, 10, ctypes.byref(o), 1, 1, 1, 1, None, None)
+    assert rc == -1
+    # a fake non-NULL context is never dereferenced before the argument checks below
+    fake = ctypes.c_void_p(0x10)
+    assert L.spotfit_fit_spots(fake, 1, 0, 1, 1, 1, -5, ctypes.byref(o), 1, 1, 1, 1, None, None) == -2
+    assert L.spotfit_fit_spots(fake, 1, 9, 1, 1, 1, 10, ctypes.byref(o), 1, 1, 1, 1, None, None) == -2
+    bad = sf.default_options(max_iter=-3)
+    assert L.spotfit_fit_spots(fake, 1, 0, 1, 1, 1, 10, ctypes.byref(bad), 1, 1, 1, 1, None, None) == -3
+    # n == 0 is a no-op even with NULL arrays
+    assert L.spotfit_fit_spots(fake, None, 0, None, None, None, 0, None, None, None, None, None,
+                               None, None) == 0
+    # NULL arrays with n > 0
+    assert L.spotfit_fit_spots(fake, None, 0, 1, 1, 1, 10, None, 1, 1, 1, 1, None, None) == -1
+    assert L.spotfit_fit_spots(fake, 1, 0, 1, 1, 1, 10, None, 1, None, 1, 1, None, None) == -1
+    assert L.spotfit_ctx_create(None, 0) == -1
+
+
+def test_version():
+    assert sf.version() >= 100
