@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale_15x15")
     ap.add_argument("--n", type=int, default=None, help="spots (default: the workload's size)")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32"])
     ap.add_argument("--tie-tau", type=float, default=0.0)
     ap.add_argument("--cpu-sample", type=int, default=1000000,
                     help="spots of the same workload fitted by the CPU oracle")
@@ -72,8 +72,10 @@ def main():
     up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     data, sizes, offs, init = up(batch.data), up(batch.sizes), up(batch.offsets), up(batch.init)
     ctx = sf.Context(0)
-    prec = sf.PREC_MIXED if a.precision == "mixed" else sf.PREC_FP32
-    opts = sf.default_options(precision=prec, max_pixels=max(9, max_px), tie_tau=a.tie_tau)
+    prec = {"fp64": sf.PREC_FP64, "mixed": sf.PREC_MIXED, "fp32": sf.PREC_FP32}[a.precision]
+    max_side = int(max(batch.sizes[:, 0].max(), batch.sizes[:, 1].max()))
+    opts = sf.default_options(precision=prec, max_pixels=max(9, max_px), max_side=max(3, max_side),
+                              tie_tau=a.tie_tau)
     out = ctx.fit_spots(data, sizes, offs, init, opts, want_evals=True)
     torch.cuda.synchronize()
 
@@ -140,7 +142,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if prec == sf.PREC_MIXED else "f32",
+        "dtype": {sf.PREC_FP64: "f64", sf.PREC_MIXED: "f32+f64", sf.PREC_FP32: "f32"}[prec],
         "data": "synthetic",
         "config": {"workload": a.workload, "spots": n, "roi": f"{batch.sizes[0,0]}x{batch.sizes[0,1]}"
                    if len(np.unique(npix)) == 1 else "mixed", "pixel_dtype": "u16",

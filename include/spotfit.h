@@ -40,7 +40,8 @@
  * detected on the host before any HIP call; n == 0 is a no-op.  Spot-level
  * problems never fail the call: a spot with w or h < 3, w*h above the
  * capacity (1024, or opt.max_pixels when smaller), an unknown model, a
- * non-finite start value or a start width <= 0 gets status SPOTFIT_BAD_INPUT,
+ * non-finite start value or a start width <= 0, or w or h above opt.max_side, gets
+ * status SPOTFIT_BAD_INPUT,
  * NaN params and chi^2, and 0 iterations.
  *
  * Asynchrony: work is enqueued on the stream and the call returns; results
@@ -75,10 +76,14 @@ typedef enum {
 
 /* Arithmetic of the fit kernel. */
 typedef enum {
-  SPOTFIT_PREC_FP32 = 0,  /* plain single precision everywhere, the paper's arithmetic    */
-  SPOTFIT_PREC_MIXED = 1  /* default: FP32 profile and derivative sums, double-precision
-                             parameters, amplitude determinant, residual, chi^2
-                             accumulation and LM solve                                  */
+  SPOTFIT_PREC_FP32 = 0,  /* per-pixel profile kernel, single precision everywhere (the
+                             paper's arithmetic)                                        */
+  SPOTFIT_PREC_MIXED = 1, /* per-pixel profile kernel: FP32 profile and derivative sums,
+                             double-precision parameters, amplitude determinant,
+                             residual, chi^2 accumulation and LM solve                  */
+  SPOTFIT_PREC_FP64 = 2   /* default: separable kernel, the profile factors into
+                             exp(column) * exp(row); every evaluation in double
+                             precision, so chi^2 comparisons see ~1e-15 relative error */
 } spotfit_precision_t;
 
 typedef enum {
@@ -111,7 +116,8 @@ typedef struct {
                                [-0.5, w-0.5], y in [-0.5, h-0.5]                           */
   int32_t max_pixels;       /* capacity promise: spots with w*h > max_pixels are
                                BAD_INPUT; smaller values select leaner kernels (1024)     */
-  int32_t reserved;
+  int32_t max_side;         /* capacity promise: spots with w or h > max_side are
+                               BAD_INPUT; smaller values select narrower lane groups (32) */
 } spotfit_options_t;
 
 /* Fill *opt with the paper's settings (Results section) and the defaults above. */

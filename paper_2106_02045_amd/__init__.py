@@ -18,7 +18,7 @@ U16, F32 = 0, 1
 SYM, ELL = 0, 1
 MAX_ITER, MAX_ERROR, MIN_DELTA, MIN_STEP, NOT_CONVERGED, BAD_INPUT = range(6)
 STATUS_NAMES = ["MAX_ITER", "MAX_ERROR", "MIN_DELTA", "MIN_STEP", "NOT_CONVERGED", "BAD_INPUT"]
-PREC_FP32, PREC_MIXED = 0, 1
+PREC_FP32, PREC_MIXED, PREC_FP64 = 0, 1, 2
 
 EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_create",
             "spotfit_ctx_destroy", "spotfit_fit_spots", "spotfit_last_error", "spotfit_version"]
@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
         ("sigma_min", ctypes.c_double),
         ("sigma_max_frac", ctypes.c_double),
         ("max_pixels", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("max_side", ctypes.c_int32),
     ]
 
 
@@ -81,7 +81,7 @@ def default_options(**kw) -> Options:
     o = Options()
     lib().spotfit_default_options(ctypes.byref(o))
     for k, v in kw.items():
-        if not hasattr(o, k) or k == "reserved":
+        if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
     return o

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -18,6 +19,8 @@ struct spotfit_ctx {
   int n_cu;
   // resident 64-lane workgroups per CU, per (ppl class, precision)
   int occupancy[5][2];
+  // resident 64-lane workgroups per CU of the separable kernel, per group size 8/16/32
+  int occ_group[3];
 };
 
 namespace {
@@ -54,7 +57,7 @@ void spotfit_default_options(spotfit_options_t* o) {
   o->max_iter = 20;               // Results section: at most 20 iterations
   o->lambda0_exp10 = -2;          // LM section: initial damping 0.01
   o->lambda_max_exp10 = 4;        // LM section: stop once damping would exceed 1e4
-  o->precision = SPOTFIT_PREC_MIXED;
+  o->precision = SPOTFIT_PREC_FP64;
   o->max_error_per_px = 1.0 / 3.0;  // Results section: chi^2 < A/3, A = pixel count
   o->min_delta = 1e-6;            // Results section: decrease below 1e-6 chi^2
   o->min_step_rel = 1e-4;         // Results section: |dp_j| < 1e-4 |p_j|
@@ -62,6 +65,7 @@ void spotfit_default_options(spotfit_options_t* o) {
   o->sigma_min = 0.3;
   o->sigma_max_frac = 1.0;
   o->max_pixels = 1024;           // Implementation section: at most 1024 pixels per fit
+  o->max_side = 32;
 }
 
 int spotfit_validate_options(const spotfit_options_t* o) {
@@ -70,7 +74,8 @@ int spotfit_validate_options(const spotfit_options_t* o) {
   if (o->lambda0_exp10 < -300 || o->lambda0_exp10 > 300 || o->lambda_max_exp10 < -300 ||
       o->lambda_max_exp10 > 300)
     return fail(SPOTFIT_E_OPTIONS, "lambda exponents not in [-300, 300]");
-  if (o->precision != SPOTFIT_PREC_FP32 && o->precision != SPOTFIT_PREC_MIXED)
+  if (o->precision != SPOTFIT_PREC_FP32 && o->precision != SPOTFIT_PREC_MIXED &&
+      o->precision != SPOTFIT_PREC_FP64)
     return fail(SPOTFIT_E_OPTIONS, "unknown precision");
   if (!std::isfinite(o->max_error_per_px) || o->max_error_per_px < 0)
     return fail(SPOTFIT_E_OPTIONS, "max_error_per_px must be finite and >= 0");
@@ -86,6 +91,8 @@ int spotfit_validate_options(const spotfit_options_t* o) {
     return fail(SPOTFIT_E_OPTIONS, "sigma_max_frac * 3 must exceed sigma_min");
   if (o->max_pixels < 9 || o->max_pixels > 1024)
     return fail(SPOTFIT_E_OPTIONS, "max_pixels not in [9, 1024]");
+  if (o->max_side < 3 || o->max_side > 32)
+    return fail(SPOTFIT_E_OPTIONS, "max_side not in [3, 32]");
   return SPOTFIT_OK;
 }
 
@@ -117,6 +124,23 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
         return fail_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
       }
       c->occupancy[i][pr] = nb > 0 ? nb : 1;
+    }
+  }
+  const int lanes[3] = {8, 16, 32};
+  for (int i = 0; i < 3; ++i) {
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sf::group_kernel_symbol(lanes[i]), 64, 0);
+    if (e != hipSuccess) {
+      delete c;
+      return fail_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    }
+    c->occ_group[i] = nb > 0 ? nb : 1;
+  }
+  if (const char* env = std::getenv("SPOTFIT_WAVES_PER_CU")) {
+    const int v = std::atoi(env);
+    if (v > 0 && v <= 64) {
+      for (int i = 0; i < 5; ++i) c->occupancy[i][0] = c->occupancy[i][1] = v;
+      for (int i = 0; i < 3; ++i) c->occ_group[i] = v;
     }
   }
   *out = c;
@@ -162,6 +186,7 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
   ka.opt.lambda0_exp10 = o.lambda0_exp10;
   ka.opt.lambda_max_exp10 = o.lambda_max_exp10;
   ka.opt.max_pixels = o.max_pixels;
+  ka.opt.max_side = o.max_side;
   ka.opt.max_error_per_px = o.max_error_per_px;
   ka.opt.min_delta = o.min_delta;
   ka.opt.min_step_rel = o.min_step_rel;
@@ -169,12 +194,23 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
   ka.opt.sigma_min = o.sigma_min;
   ka.opt.sigma_max_frac = o.sigma_max_frac;
 
-  const int ppl = sf::ppl_for_pixels(o.max_pixels);
-  const int pr = o.precision == SPOTFIT_PREC_MIXED ? 1 : 0;
-  // persistent grid: as many one-wave workgroups as can be resident at once
-  const int64_t resident = (int64_t)ctx->n_cu * ctx->occupancy[ppl_index(ppl)][pr];
-  const int grid = (int)(n < resident ? n : resident);
-  hipError_t e = sf::launch_wave_kernel(ppl, o.precision, ka, grid, (hipStream_t)stream);
+  hipError_t e;
+  if (o.precision == SPOTFIT_PREC_FP64) {
+    const int lanes = sf::group_lanes_for_side(o.max_side);
+    const int gidx = lanes == 8 ? 0 : lanes == 16 ? 1 : 2;
+    const int64_t per_wave = 64 / lanes;
+    const int64_t need = (n + per_wave - 1) / per_wave;
+    // persistent grid: as many one-wave workgroups as can be resident at once
+    const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_group[gidx];
+    const int grid = (int)(need < resident ? need : resident);
+    e = sf::launch_group_kernel(lanes, ka, grid, (hipStream_t)stream);
+  } else {
+    const int ppl = sf::ppl_for_pixels(o.max_pixels);
+    const int pr = o.precision == SPOTFIT_PREC_MIXED ? 1 : 0;
+    const int64_t resident = (int64_t)ctx->n_cu * ctx->occupancy[ppl_index(ppl)][pr];
+    const int grid = (int)(n < resident ? n : resident);
+    e = sf::launch_wave_kernel(ppl, o.precision, ka, grid, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return fail_hip(e, "fit kernel launch");
   return SPOTFIT_OK;
 }

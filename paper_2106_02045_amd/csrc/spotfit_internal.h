@@ -14,6 +14,8 @@ struct KOpts {
   int lambda0_exp10;
   int lambda_max_exp10;
   int max_pixels;
+  int max_side;
+  int pad_;
   double max_error_per_px;
   double min_delta;
   double min_step_rel;
@@ -43,5 +45,10 @@ struct KArgs {
 int ppl_for_pixels(int max_pixels);
 const void* wave_kernel_symbol(int ppl, int precision);
 hipError_t launch_wave_kernel(int ppl, int precision, const KArgs& ka, int grid, hipStream_t st);
+
+// Lanes per spot of the separable kernel able to hold spots with w, h <= max_side.
+int group_lanes_for_side(int max_side);
+const void* group_kernel_symbol(int lanes);
+hipError_t launch_group_kernel(int lanes, const KArgs& ka, int grid, hipStream_t st);
 
 }  // namespace sf

@@ -28,14 +28,20 @@ def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None) -> 
     rp = r["params"]
     n = len(rp)
     bad_in = r["status"] == 5
-    dxy = np.abs(gp[:, :2] - rp[:, :2]).max(1)
-    rel = _rel(gp[:, 2:6], rp[:, 2:6])
-    # beta can be ~0 on low-background spots: compare it relative to the spot's level
-    scale_b = np.maximum(np.abs(rp[:, 5]), 1e-3 * np.abs(rp[:, 4]))
-    rel[:, 3] = np.abs(gp[:, 5] - rp[:, 5]) / scale_b
+    both_nan = np.isnan(gp) & np.isnan(rp)
+    dxy = np.where(both_nan[:, :2], 0.0, np.abs(gp[:, :2] - rp[:, :2])).max(1)
+    # widths relative to themselves; amplitude and background relative to the
+    # spot's level, so that a degenerate spot (alpha = 0, or beta ~ 0) compares sanely
+    level = np.maximum(np.abs(rp[:, 4]), np.abs(rp[:, 5]))
+    rel_s = _rel(gp[:, 2:4], rp[:, 2:4])
+    rel_a = np.abs(gp[:, 4] - rp[:, 4]) / np.maximum(np.abs(rp[:, 4]), 1e-3 * level)
+    rel_b = np.abs(gp[:, 5] - rp[:, 5]) / np.maximum(np.abs(rp[:, 5]), 1e-3 * level)
+    rel = np.concatenate([rel_s, rel_a[:, None], rel_b[:, None]], 1)
+    rel = np.where(both_nan[:, 2:6], 0.0, rel)
     relmax = rel.max(1)
-    rchi = _rel(np.asarray(g["chi2"], np.float64), r["chi2"])
-    rchi = np.where((r["chi2"] == 0) & (np.asarray(g["chi2"]) == 0), 0.0, rchi)
+    gc = np.asarray(g["chi2"], np.float64)
+    rchi = np.abs(gc - r["chi2"]) / np.maximum(np.abs(r["chi2"]), 1e-6)
+    rchi = np.where(np.isnan(gc) & np.isnan(r["chi2"]), 0.0, rchi)
     same_status = g["status"] == r["status"]
     same_iters = g["iters"] == r["iters"]
     knife = (r["margin_chi"] < chi_band) | (r["margin_step"] < step_band)

@@ -61,7 +61,7 @@ def test_default_options_are_the_papers():
     assert o.max_iter == 20 and o.lambda0_exp10 == -2 and o.lambda_max_exp10 == 4
     assert o.min_delta == 1e-6 and o.min_step_rel == 1e-4
     assert o.max_error_per_px == pytest.approx(1 / 3)
-    assert o.max_pixels == 1024 and o.precision == sf.PREC_MIXED
+    assert o.max_pixels == 1024 and o.max_side == 32 and o.precision == sf.PREC_FP64
     assert sf.lib().spotfit_validate_options(ctypes.byref(o)) == 0
 
 
@@ -69,6 +69,7 @@ def test_default_options_are_the_papers():
     ("max_iter", -1), ("max_iter", 5000), ("precision", 7), ("min_delta", 1.0),
     ("min_delta", -1e-3), ("tie_tau", 1.5), ("sigma_min", 0.0), ("max_pixels", 2000),
     ("max_pixels", 4), ("max_error_per_px", float("nan")), ("sigma_max_frac", 0.05),
+    ("max_side", 2), ("max_side", 33),
 ])
 def test_bad_options_rejected(field, value):
     o = sf.default_options()
