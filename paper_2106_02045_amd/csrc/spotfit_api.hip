@@ -19,7 +19,9 @@ struct spotfit_ctx {
   int n_cu;
   // resident 64-lane workgroups per CU, per (ppl class, precision)
   int occupancy[5][2];
-  // resident 64-lane workgroups per CU of the separable kernel, per group size 8/16/32
+  // separable kernel, per group size 8/16/32: register-cap variant (min waves per
+  // SIMD) and its resident 64-lane workgroups per CU
+  int wpe_group[3];
   int occ_group[3];
 };
 
@@ -127,9 +129,15 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
     }
   }
   const int lanes[3] = {8, 16, 32};
+  int wpe_env = 0;
+  if (const char* env = std::getenv("SPOTFIT_GROUP_WPE")) wpe_env = std::atoi(env);
+  // register caps measured best on MI355X: 8 lanes 2, 16 lanes 3, 32 lanes 3 waves per SIMD
+  const int wpe_default[3] = {2, 3, 3};
   for (int i = 0; i < 3; ++i) {
+    c->wpe_group[i] = (wpe_env >= 1 && wpe_env <= 4) ? wpe_env : wpe_default[i];
     int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sf::group_kernel_symbol(lanes[i]), 64, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, sf::group_kernel_symbol(lanes[i], c->wpe_group[i]), 64, 0);
     if (e != hipSuccess) {
       delete c;
       return fail_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
@@ -203,7 +211,7 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
     // persistent grid: as many one-wave workgroups as can be resident at once
     const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_group[gidx];
     const int grid = (int)(need < resident ? need : resident);
-    e = sf::launch_group_kernel(lanes, ka, grid, (hipStream_t)stream);
+    e = sf::launch_group_kernel(lanes, ctx->wpe_group[gidx], ka, grid, (hipStream_t)stream);
   } else {
     const int ppl = sf::ppl_for_pixels(o.max_pixels);
     const int pr = o.precision == SPOTFIT_PREC_MIXED ? 1 : 0;

@@ -157,8 +157,8 @@ __device__ __forceinline__ int tri_j(int t) {
 //   9..12     Yq1..Yq4 = sum dy^k ey^2                    (Yq0 = sum ey^2)
 //   13, 14    B_x = sum dx ex t,  B_sx = sum dx^2 ex t    (t = sum_r g ey per column)
 //   15, 0     B_y = sum ex t_y,   B_sy = sum ex t_yy      (t_y, t_yy: (r-y), (r-y)^2 weights)
-template <int L>
-__global__ __launch_bounds__(64) void fit_group_kernel(KArgs ka) {
+template <int L, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_group_kernel(KArgs ka) {
   constexpr int G = 64 / L;  // groups (spots in flight) per wavefront
   constexpr int HM = L;      // rows held per lane
   constexpr double kC0 = 0.5 * (HM - 1);  // row origin of the bilinear row moments
@@ -514,10 +514,30 @@ __global__ __launch_bounds__(64) void fit_group_kernel(KArgs ka) {
   }
 }
 
-template <int L>
-static hipError_t launch_l(const KArgs& ka, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((fit_group_kernel<L>), dim3(grid), dim3(64), 0, st, ka);
+template <int L, int WPE>
+static hipError_t launch_lw(const KArgs& ka, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((fit_group_kernel<L, WPE>), dim3(grid), dim3(64), 0, st, ka);
   return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_l(int wpe, const KArgs& ka, int grid, hipStream_t st) {
+  switch (wpe) {
+    case 2: return launch_lw<L, 2>(ka, grid, st);
+    case 3: return launch_lw<L, 3>(ka, grid, st);
+    case 4: return launch_lw<L, 4>(ka, grid, st);
+    default: return launch_lw<L, 1>(ka, grid, st);
+  }
+}
+
+template <int L>
+static const void* symbol_l(int wpe) {
+  switch (wpe) {
+    case 2: return reinterpret_cast<const void*>(&fit_group_kernel<L, 2>);
+    case 3: return reinterpret_cast<const void*>(&fit_group_kernel<L, 3>);
+    case 4: return reinterpret_cast<const void*>(&fit_group_kernel<L, 4>);
+    default: return reinterpret_cast<const void*>(&fit_group_kernel<L, 1>);
+  }
 }
 
 }  // namespace grp
@@ -528,19 +548,19 @@ int group_lanes_for_side(int max_side) {
   return 32;
 }
 
-const void* group_kernel_symbol(int lanes) {
+const void* group_kernel_symbol(int lanes, int wpe) {
   switch (lanes) {
-    case 8: return reinterpret_cast<const void*>(&grp::fit_group_kernel<8>);
-    case 16: return reinterpret_cast<const void*>(&grp::fit_group_kernel<16>);
-    default: return reinterpret_cast<const void*>(&grp::fit_group_kernel<32>);
+    case 8: return grp::symbol_l<8>(wpe);
+    case 16: return grp::symbol_l<16>(wpe);
+    default: return grp::symbol_l<32>(wpe);
   }
 }
 
-hipError_t launch_group_kernel(int lanes, const KArgs& ka, int grid, hipStream_t st) {
+hipError_t launch_group_kernel(int lanes, int wpe, const KArgs& ka, int grid, hipStream_t st) {
   switch (lanes) {
-    case 8: return grp::launch_l<8>(ka, grid, st);
-    case 16: return grp::launch_l<16>(ka, grid, st);
-    default: return grp::launch_l<32>(ka, grid, st);
+    case 8: return grp::launch_l<8>(wpe, ka, grid, st);
+    case 16: return grp::launch_l<16>(wpe, ka, grid, st);
+    default: return grp::launch_l<32>(wpe, ka, grid, st);
   }
 }
 

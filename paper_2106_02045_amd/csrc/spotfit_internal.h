@@ -48,7 +48,8 @@ hipError_t launch_wave_kernel(int ppl, int precision, const KArgs& ka, int grid,
 
 // Lanes per spot of the separable kernel able to hold spots with w, h <= max_side.
 int group_lanes_for_side(int max_side);
-const void* group_kernel_symbol(int lanes);
-hipError_t launch_group_kernel(int lanes, const KArgs& ka, int grid, hipStream_t st);
+// wpe: minimum waves per SIMD the register allocation must allow (1..4).
+const void* group_kernel_symbol(int lanes, int wpe);
+hipError_t launch_group_kernel(int lanes, int wpe, const KArgs& ka, int grid, hipStream_t st);
 
 }  // namespace sf
