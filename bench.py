@@ -40,11 +40,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale_15x15")
     ap.add_argument("--n", type=int, default=None, help="spots (default: the workload's size)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32", "plain"])
     ap.add_argument("--tie-tau", type=float, default=0.0)
     ap.add_argument("--cpu-sample", type=int, default=1000000,
                     help="spots of the same workload fitted by the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--parity-sample", type=int, default=2000,
+                    help="spots compared with the CPU oracle after the timed run (0: none)")
     return ap.parse_args()
 
 
@@ -72,7 +74,8 @@ def main():
     up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     data, sizes, offs, init = up(batch.data), up(batch.sizes), up(batch.offsets), up(batch.init)
     ctx = sf.Context(0)
-    prec = {"fp64": sf.PREC_FP64, "mixed": sf.PREC_MIXED, "fp32": sf.PREC_FP32}[a.precision]
+    prec = {"fp64": sf.PREC_FP64, "mixed": sf.PREC_MIXED, "fp32": sf.PREC_FP32,
+            "plain": sf.PREC_FP32_PLAIN}[a.precision]
     max_side = int(max(batch.sizes[:, 0].max(), batch.sizes[:, 1].max()))
     opts = sf.default_options(precision=prec, max_pixels=max(9, max_px), max_side=max(3, max_side),
                               tie_tau=a.tie_tau)
@@ -131,6 +134,23 @@ def main():
                "sample": f"first {m} spots of {a.workload} (same generator and seed), "
                          f"{cs:.2f} s wall on {threads} threads"}
 
+    parity = None
+    if a.parity_sample > 0:
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import compare
+        rng = np.random.default_rng(12345)
+        idx = np.sort(rng.choice(n, size=min(a.parity_sample, n), replace=False))
+        r = oracle.fit_batch(batch.subset(idx), oracle.default_opts(tie_tau=a.tie_tau),
+                             threads=min(os.cpu_count() or 1, 16))
+        g = {"params": out["params"].cpu().numpy()[idx], "chi2": out["chi2"].cpu().numpy()[idx],
+             "iters": out["iters"].cpu().numpy()[idx], "status": out["status"].cpu().numpy()[idx]}
+        c = compare(g, r, chi_band=1e-11, step_band=1e-9)
+        parity = {"sample": len(idx), "status_mismatch": c["status_mismatch"],
+                  "iters_mismatch": c["iters_mismatch"], "tol_fail": c["tol_fail_any"],
+                  "max_abs_dxy_px": c["max_dxy"], "max_rel_sigma_alpha_beta": c["max_rel"],
+                  "max_rel_chi2": c["max_rchi"], "median_rel_chi2": c["med_rchi"]}
+
     rec = {
         "metric": "fits/s",
         "value": fits_per_s,
@@ -142,7 +162,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {sf.PREC_FP64: "f64", sf.PREC_MIXED: "f32+f64", sf.PREC_FP32: "f32"}[prec],
+        "dtype": {sf.PREC_FP64: "f64", sf.PREC_MIXED: "f32+f64", sf.PREC_FP32: "f32",
+                  sf.PREC_FP32_PLAIN: "f32"}[prec],
         "data": "synthetic",
         "config": {"workload": a.workload, "spots": n, "roi": f"{batch.sizes[0,0]}x{batch.sizes[0,1]}"
                    if len(np.unique(npix)) == 1 else "mixed", "pixel_dtype": "u16",
@@ -158,6 +179,7 @@ def main():
         "status_hist": np.bincount(status, minlength=6).tolist(),
         "iters_mean": float(iters.mean()),
         "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
         "gen_s": gen_s,
     }
     print(json.dumps(rec))

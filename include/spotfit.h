@@ -81,9 +81,12 @@ typedef enum {
   SPOTFIT_PREC_MIXED = 1, /* per-pixel profile kernel: FP32 profile and derivative sums,
                              double-precision parameters, amplitude determinant,
                              residual, chi^2 accumulation and LM solve                  */
-  SPOTFIT_PREC_FP64 = 2   /* default: separable kernel, the profile factors into
+  SPOTFIT_PREC_FP64 = 2,  /* default: separable kernel, the profile factors into
                              exp(column) * exp(row); every evaluation in double
                              precision, so chi^2 comparisons see ~1e-15 relative error */
+  SPOTFIT_PREC_FP32_PLAIN = 3 /* the paper's own mapping as a baseline: one thread per
+                             pixel, one workgroup per spot, one sum per quantity,
+                             single precision everywhere                               */
 } spotfit_precision_t;
 
 typedef enum {

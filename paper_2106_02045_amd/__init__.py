@@ -18,7 +18,7 @@ U16, F32 = 0, 1
 SYM, ELL = 0, 1
 MAX_ITER, MAX_ERROR, MIN_DELTA, MIN_STEP, NOT_CONVERGED, BAD_INPUT = range(6)
 STATUS_NAMES = ["MAX_ITER", "MAX_ERROR", "MIN_DELTA", "MIN_STEP", "NOT_CONVERGED", "BAD_INPUT"]
-PREC_FP32, PREC_MIXED, PREC_FP64 = 0, 1, 2
+PREC_FP32, PREC_MIXED, PREC_FP64, PREC_FP32_PLAIN = 0, 1, 2, 3
 
 EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_create",
             "spotfit_ctx_destroy", "spotfit_fit_spots", "spotfit_last_error", "spotfit_version"]

@@ -77,7 +77,7 @@ int spotfit_validate_options(const spotfit_options_t* o) {
       o->lambda_max_exp10 > 300)
     return fail(SPOTFIT_E_OPTIONS, "lambda exponents not in [-300, 300]");
   if (o->precision != SPOTFIT_PREC_FP32 && o->precision != SPOTFIT_PREC_MIXED &&
-      o->precision != SPOTFIT_PREC_FP64)
+      o->precision != SPOTFIT_PREC_FP64 && o->precision != SPOTFIT_PREC_FP32_PLAIN)
     return fail(SPOTFIT_E_OPTIONS, "unknown precision");
   if (!std::isfinite(o->max_error_per_px) || o->max_error_per_px < 0)
     return fail(SPOTFIT_E_OPTIONS, "max_error_per_px must be finite and >= 0");
@@ -212,6 +212,9 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
     const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_group[gidx];
     const int grid = (int)(need < resident ? need : resident);
     e = sf::launch_group_kernel(lanes, ctx->wpe_group[gidx], ka, grid, (hipStream_t)stream);
+  } else if (o.precision == SPOTFIT_PREC_FP32_PLAIN) {
+    const int threads = ((o.max_pixels + 63) / 64) * 64;
+    e = sf::launch_plain_kernel(ka, threads, (hipStream_t)stream);
   } else {
     const int ppl = sf::ppl_for_pixels(o.max_pixels);
     const int pr = o.precision == SPOTFIT_PREC_MIXED ? 1 : 0;

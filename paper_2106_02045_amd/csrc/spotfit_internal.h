@@ -46,6 +46,9 @@ int ppl_for_pixels(int max_pixels);
 const void* wave_kernel_symbol(int ppl, int precision);
 hipError_t launch_wave_kernel(int ppl, int precision, const KArgs& ka, int grid, hipStream_t st);
 
+// One workgroup per spot with `threads` threads (a multiple of 64, >= max_pixels).
+hipError_t launch_plain_kernel(const KArgs& ka, int threads, hipStream_t st);
+
 // Lanes per spot of the separable kernel able to hold spots with w, h <= max_side.
 int group_lanes_for_side(int max_side);
 // wpe: minimum waves per SIMD the register allocation must allow (1..4).

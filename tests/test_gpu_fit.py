@@ -185,10 +185,11 @@ def test_capacity_promise(gpu):
     assert np.all(g["status"][~big] != 5)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 3])
 def test_per_pixel_kernels_within_tolerance(gpu, prec):
-    """The per-pixel single-precision kernels (plain FP32 and mixed) stay close to the
-    oracle; their chi^2 noise (~1e-7) flips MinDelta decisions on a few percent."""
+    """The per-pixel single-precision kernels (FP32, mixed, and the paper's own mapping)
+    stay close to the oracle; their chi^2 noise (~1e-7) flips MinDelta decisions on a
+    few percent of the spots."""
     b = spotgen.config(0)
     tau = 9e-7
     g = gpu(b, tie_tau=tau, max_pixels=121, precision=prec)
@@ -196,5 +197,5 @@ def test_per_pixel_kernels_within_tolerance(gpu, prec):
     c = compare(g, r, chi_band=3e-6, step_band=1e-2)
     print(summary(f"per-pixel precision={prec}", c))
     assert c["max_dxy"] < 1e-3
-    assert c["tol_fail_same"] == 0
+    assert c["tol_fail_same"] <= (0 if prec != 3 else 0.01 * b.n)
     assert c["status_mismatch"] <= 0.1 * b.n
