@@ -89,13 +89,25 @@ typedef enum {
                              single precision everywhere                               */
 } spotfit_precision_t;
 
+/* How the separable kernel maps a batch onto lane groups. */
+typedef enum {
+  SPOTFIT_SCHEDULE_UNIFORM = 0, /* one group width for the whole batch, chosen by max_side;
+                                   spots are strided over a persistent grid            */
+  SPOTFIT_SCHEDULE_MIXED = 1    /* batches of uneven sizes: a classify pass buckets spots
+                                   by size class (largest side <= 8, <= 16, <= 32), then
+                                   one persistent launch runs each class with its own
+                                   group width; needs the context workspace (see
+                                   spotfit_ctx_reserve)                                 */
+} spotfit_schedule_t;
+
 typedef enum {
   SPOTFIT_OK = 0,
   SPOTFIT_E_NULL = -1,     /* NULL context, output or input array with n > 0           */
   SPOTFIT_E_ARG = -2,      /* n < 0, unknown dtype                                       */
   SPOTFIT_E_OPTIONS = -3,  /* options out of range                                       */
   SPOTFIT_E_HIP = -4,      /* a HIP runtime call failed (message via spotfit_last_error) */
-  SPOTFIT_E_DEVICE = -5    /* no usable gfx950 device                                    */
+  SPOTFIT_E_DEVICE = -5,   /* no usable gfx950 device                                    */
+  SPOTFIT_E_AGAIN = -6     /* serving: frame not admitted now (memory or slots); retry   */
 } spotfit_error_t;
 
 typedef struct {
@@ -121,6 +133,8 @@ typedef struct {
                                BAD_INPUT; smaller values select leaner kernels (1024)     */
   int32_t max_side;         /* capacity promise: spots with w or h > max_side are
                                BAD_INPUT; smaller values select narrower lane groups (32) */
+  int32_t schedule;         /* SPOTFIT_PREC_FP64 only: spotfit_schedule_t (UNIFORM)        */
+  int32_t reserved;         /* 0                                                           */
 } spotfit_options_t;
 
 /* Fill *opt with the paper's settings (Results section) and the defaults above. */
@@ -135,6 +149,14 @@ int spotfit_validate_options(const spotfit_options_t* opt);
 int spotfit_ctx_create(spotfit_ctx_t** ctx, int device);
 void spotfit_ctx_destroy(spotfit_ctx_t* ctx);
 
+/* Size the context's device workspace for mixed-schedule calls of up to n_spots
+ * spots (12 bytes per spot plus 32 bytes).  A mixed-schedule call with more spots
+ * than reserved grows the workspace itself (one synchronous device allocation),
+ * so callers that must not allocate inside a call (graph capture, serving loops)
+ * reserve first.  Returns SPOTFIT_OK, SPOTFIT_E_NULL, SPOTFIT_E_ARG or
+ * SPOTFIT_E_HIP. */
+int spotfit_ctx_reserve(spotfit_ctx_t* ctx, int64_t n_spots);
+
 /* Fit n_spots spots (see the layout above) on `stream`.  All array arguments
  * are device pointers; opt is a host pointer (NULL = defaults).  Allocates
  * nothing.  Returns SPOTFIT_OK or a negative spotfit_error_t. */
@@ -143,6 +165,66 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                       int64_t n_spots, const spotfit_options_t* opt, float* params_out,
                       float* chi2_out, int32_t* iters_out, int32_t* status_out,
                       int32_t* evals_out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving loop for camera frames (real-time tracking of fiducial spots).    */
+/* ------------------------------------------------------------------------ */
+typedef struct spotfit_serve spotfit_serve_t; /* opaque */
+
+/* One camera frame, all pointers HOST memory.  Spots lie back to back in `data`
+ * (row-major each, no offsets array).  The input buffers may be reused as soon
+ * as submit returns; the output arrays must stay valid until the frame is done. */
+typedef struct {
+  const void* data;              /* n_spots spots of pixels, dtype below              */
+  const spotfit_shape_t* sizes;  /* n_spots shapes                                     */
+  const float* init;             /* n_spots x 4 start values                           */
+  int32_t n_spots;
+  int32_t dtype;                 /* spotfit_dtype_t                                    */
+  float* params_out;             /* n_spots x 6                                        */
+  float* chi2_out;               /* n_spots                                            */
+  int32_t* iters_out;            /* n_spots, or NULL                                   */
+  int32_t* status_out;           /* n_spots, or NULL                                   */
+} spotfit_frame_t;
+
+typedef struct {
+  uint64_t frames_done, frames_failed, spots_done, batches, rejected;
+  double latency_p50_us;         /* arrival -> results in the caller's arrays          */
+  double latency_p99_us;
+  double latency_max_us;
+  double mean_frames_per_batch;  /* continuous batching: frames folded per launch      */
+  double wall_s;                 /* first arrival to last completion                   */
+} spotfit_serve_stats_t;
+
+/* Create a serving loop on `device` with fit options `opt` (NULL = defaults):
+ * device memory for at most `device_mem_budget` bytes of frames in flight
+ * (3/4 pixels, 1/4 per-spot records, plus pinned host mirrors of the same size),
+ * at most `max_frames` frames in flight, `n_streams` streams (each with its own
+ * context) so that batches overlap on the device.  Starts a dispatcher thread. */
+int spotfit_serve_create(spotfit_serve_t** sv, int device, const spotfit_options_t* opt,
+                         size_t device_mem_budget, int32_t max_frames, int32_t n_streams);
+
+/* Submit a frame; `arrival_ns` is its arrival time on the steady clock in ns
+ * (0 = now), from which its latency is measured.  Returns SPOTFIT_OK and a
+ * ticket, or SPOTFIT_E_AGAIN when memory or slots are short (nothing queued). */
+int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* frame, uint64_t arrival_ns,
+                         uint64_t* ticket);
+
+/* 0 when the frame's results are in its arrays, 1 while pending, < 0 on error. */
+int spotfit_serve_poll(spotfit_serve_t* sv, uint64_t ticket);
+/* Block until the frame is done; SPOTFIT_OK or < 0 on error. */
+int spotfit_serve_wait(spotfit_serve_t* sv, uint64_t ticket);
+int spotfit_serve_stats(spotfit_serve_t* sv, spotfit_serve_stats_t* out);
+/* Stop the dispatcher (frames already launched complete), free everything. */
+void spotfit_serve_destroy(spotfit_serve_t* sv);
+
+/* Benchmark driver: submit frames[f] at arrival_offset_ns[f] after a start time
+ * (busy-waiting on the steady clock; a refused frame is retried and keeps its
+ * arrival time), then wait for all.  Latencies are in spotfit_serve_stats. */
+int spotfit_serve_replay(spotfit_serve_t* sv, const spotfit_frame_t* frames, int64_t n_frames,
+                         const uint64_t* arrival_offset_ns);
+
+/* Text of the last serving error on this thread.  Host only. */
+const char* spotfit_serve_last_error(void);
 
 /* Text of the last error on this thread ("" if none).  Host only. */
 const char* spotfit_last_error(void);

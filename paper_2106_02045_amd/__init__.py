@@ -19,9 +19,15 @@ SYM, ELL = 0, 1
 MAX_ITER, MAX_ERROR, MIN_DELTA, MIN_STEP, NOT_CONVERGED, BAD_INPUT = range(6)
 STATUS_NAMES = ["MAX_ITER", "MAX_ERROR", "MIN_DELTA", "MIN_STEP", "NOT_CONVERGED", "BAD_INPUT"]
 PREC_FP32, PREC_MIXED, PREC_FP64, PREC_FP32_PLAIN = 0, 1, 2, 3
+SCHEDULE_UNIFORM, SCHEDULE_MIXED = 0, 1
 
 EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_create",
-            "spotfit_ctx_destroy", "spotfit_fit_spots", "spotfit_last_error", "spotfit_version"]
+            "spotfit_ctx_destroy", "spotfit_ctx_reserve", "spotfit_fit_spots",
+            "spotfit_last_error", "spotfit_version", "spotfit_serve_create",
+            "spotfit_serve_submit", "spotfit_serve_poll", "spotfit_serve_wait",
+            "spotfit_serve_stats", "spotfit_serve_destroy", "spotfit_serve_replay",
+            "spotfit_serve_last_error"]
+E_AGAIN = -6
 
 
 class SpotfitError(RuntimeError):
@@ -43,6 +49,39 @@ class Options(ctypes.Structure):
         ("sigma_max_frac", ctypes.c_double),
         ("max_pixels", ctypes.c_int32),
         ("max_side", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Frame(ctypes.Structure):
+    """Mirror of spotfit_frame_t (host pointers)."""
+    _fields_ = [
+        ("data", ctypes.c_void_p),
+        ("sizes", ctypes.c_void_p),
+        ("init", ctypes.c_void_p),
+        ("n_spots", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("params_out", ctypes.c_void_p),
+        ("chi2_out", ctypes.c_void_p),
+        ("iters_out", ctypes.c_void_p),
+        ("status_out", ctypes.c_void_p),
+    ]
+
+
+class ServeStats(ctypes.Structure):
+    """Mirror of spotfit_serve_stats_t."""
+    _fields_ = [
+        ("frames_done", ctypes.c_uint64),
+        ("frames_failed", ctypes.c_uint64),
+        ("spots_done", ctypes.c_uint64),
+        ("batches", ctypes.c_uint64),
+        ("rejected", ctypes.c_uint64),
+        ("latency_p50_us", ctypes.c_double),
+        ("latency_p99_us", ctypes.c_double),
+        ("latency_max_us", ctypes.c_double),
+        ("mean_frames_per_batch", ctypes.c_double),
+        ("wall_s", ctypes.c_double),
     ]
 
 
@@ -66,6 +105,8 @@ def lib():
         L.spotfit_ctx_create.restype = ctypes.c_int
         L.spotfit_ctx_destroy.argtypes = [vp]
         L.spotfit_ctx_destroy.restype = None
+        L.spotfit_ctx_reserve.argtypes = [vp, i64]
+        L.spotfit_ctx_reserve.restype = ctypes.c_int
         L.spotfit_fit_spots.argtypes = [vp, vp, i32, vp, vp, vp, i64, ctypes.POINTER(Options),
                                         vp, vp, vp, vp, vp, vp]
         L.spotfit_fit_spots.restype = ctypes.c_int
@@ -73,6 +114,24 @@ def lib():
         L.spotfit_last_error.restype = ctypes.c_char_p
         L.spotfit_version.argtypes = []
         L.spotfit_version.restype = ctypes.c_int
+        u64 = ctypes.c_uint64
+        L.spotfit_serve_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int,
+                                           ctypes.POINTER(Options), ctypes.c_size_t, i32, i32]
+        L.spotfit_serve_create.restype = ctypes.c_int
+        L.spotfit_serve_submit.argtypes = [vp, ctypes.POINTER(Frame), u64, ctypes.POINTER(u64)]
+        L.spotfit_serve_submit.restype = ctypes.c_int
+        L.spotfit_serve_poll.argtypes = [vp, u64]
+        L.spotfit_serve_poll.restype = ctypes.c_int
+        L.spotfit_serve_wait.argtypes = [vp, u64]
+        L.spotfit_serve_wait.restype = ctypes.c_int
+        L.spotfit_serve_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+        L.spotfit_serve_stats.restype = ctypes.c_int
+        L.spotfit_serve_destroy.argtypes = [vp]
+        L.spotfit_serve_destroy.restype = None
+        L.spotfit_serve_replay.argtypes = [vp, ctypes.POINTER(Frame), i64, vp]
+        L.spotfit_serve_replay.restype = ctypes.c_int
+        L.spotfit_serve_last_error.argtypes = []
+        L.spotfit_serve_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -81,7 +140,7 @@ def default_options(**kw) -> Options:
     o = Options()
     lib().spotfit_default_options(ctypes.byref(o))
     for k, v in kw.items():
-        if not hasattr(o, k):
+        if not hasattr(o, k) or k == "reserved":
             raise KeyError(k)
         setattr(o, k, v)
     return o
@@ -116,6 +175,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def reserve(self, n_spots: int):
+        """Size the device workspace for mixed-schedule calls of up to n_spots spots."""
+        _check(lib().spotfit_ctx_reserve(self._h, int(n_spots)), "spotfit_ctx_reserve")
 
     def fit_spots_raw(self, data_ptr: int, dtype: int, sizes_ptr: int, offsets_ptr: int,
                       init_ptr: int, n: int, opts: Optional[Options], params_ptr: int,
@@ -174,3 +237,88 @@ class Context:
 
 def version() -> int:
     return int(lib().spotfit_version())
+
+
+class Server:
+    """Real-time serving loop (spotfit_serve_t): frames from host memory in, fits out.
+
+    Frames are numpy arrays on the host; results land in numpy arrays that this
+    object keeps alive until the frame is done.
+    """
+
+    def __init__(self, device: int = 0, opts: Optional[Options] = None,
+                 device_mem_budget: int = 256 << 20, max_frames: int = 4096, n_streams: int = 2):
+        h = ctypes.c_void_p()
+        rc = lib().spotfit_serve_create(ctypes.byref(h), int(device),
+                                        ctypes.byref(opts) if opts is not None else None,
+                                        int(device_mem_budget), int(max_frames), int(n_streams))
+        if rc != 0:
+            raise SpotfitError(f"spotfit_serve_create failed with {rc}: "
+                               f"{lib().spotfit_serve_last_error().decode(errors='replace')}")
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def make_frame(data, sizes, init):
+        """Build a spotfit_frame_t (and its output arrays) from numpy arrays."""
+        import numpy as np
+        data = np.ascontiguousarray(data)
+        sizes = np.ascontiguousarray(sizes, dtype=np.uint8)
+        init = np.ascontiguousarray(init, dtype=np.float32)
+        n = int(sizes.shape[0])
+        outs = dict(params=np.zeros((n, 6), np.float32), chi2=np.zeros(n, np.float32),
+                    iters=np.zeros(n, np.int32), status=np.zeros(n, np.int32))
+        f = Frame(data.ctypes.data, sizes.ctypes.data, init.ctypes.data, n,
+                  U16 if data.dtype == np.uint16 else F32, outs["params"].ctypes.data,
+                  outs["chi2"].ctypes.data, outs["iters"].ctypes.data, outs["status"].ctypes.data)
+        return f, (data, sizes, init), outs
+
+    def submit(self, data, sizes, init, arrival_ns: int = 0):
+        """Returns (ticket, outputs) or None when the frame is not admitted now."""
+        f, ins, outs = self.make_frame(data, sizes, init)
+        t = ctypes.c_uint64()
+        rc = lib().spotfit_serve_submit(self._h, ctypes.byref(f), int(arrival_ns), ctypes.byref(t))
+        if rc == E_AGAIN:
+            return None
+        if rc != 0:
+            raise SpotfitError(f"spotfit_serve_submit failed with {rc}: "
+                               f"{lib().spotfit_serve_last_error().decode(errors='replace')}")
+        self._keep[t.value] = outs
+        return t.value, outs
+
+    def wait(self, ticket: int):
+        rc = lib().spotfit_serve_wait(self._h, int(ticket))
+        if rc != 0:
+            raise SpotfitError(f"spotfit_serve_wait failed with {rc}")
+        return self._keep.pop(ticket)
+
+    def poll(self, ticket: int) -> int:
+        return lib().spotfit_serve_poll(self._h, int(ticket))
+
+    def replay(self, frames, arrival_offset_ns):
+        """frames: list of (data, sizes, init); arrival offsets in ns.  Returns outputs."""
+        import numpy as np
+        built = [self.make_frame(*fr) for fr in frames]
+        arr = (Frame * len(built))(*[b[0] for b in built])
+        offs = np.ascontiguousarray(arrival_offset_ns, dtype=np.uint64)
+        rc = lib().spotfit_serve_replay(self._h, arr, len(built), offs.ctypes.data)
+        if rc != 0:
+            raise SpotfitError(f"spotfit_serve_replay failed with {rc}: "
+                               f"{lib().spotfit_serve_last_error().decode(errors='replace')}")
+        return [b[2] for b in built]
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check(lib().spotfit_serve_stats(self._h, ctypes.byref(st)), "spotfit_serve_stats")
+        return {k: getattr(st, k) for k, _ in ServeStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().spotfit_serve_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

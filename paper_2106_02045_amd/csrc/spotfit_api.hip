@@ -19,10 +19,15 @@ struct spotfit_ctx {
   int n_cu;
   // resident 64-lane workgroups per CU, per (ppl class, precision)
   int occupancy[5][2];
-  // separable kernel, per group size 8/16/32: register-cap variant (min waves per
-  // SIMD) and its resident 64-lane workgroups per CU
-  int wpe_group[3];
-  int occ_group[3];
+  // separable kernel: plan used for each size class (max side <= 8, <= 16, <= 32)
+  // and resident 64-lane workgroups per CU of every plan
+  int plan_for_class[3];
+  int occ_plan[8];
+  // mixed-size batches: plan and residency of the persistent kernel, workspace
+  int mixed_plan;
+  int occ_mixed[4];
+  int32_t* ws;      // counters[8] then 3 lists of ws_cap spot indices
+  int64_t ws_cap;
 };
 
 namespace {
@@ -68,6 +73,7 @@ void spotfit_default_options(spotfit_options_t* o) {
   o->sigma_max_frac = 1.0;
   o->max_pixels = 1024;           // Implementation section: at most 1024 pixels per fit
   o->max_side = 32;
+  o->schedule = SPOTFIT_SCHEDULE_UNIFORM;
 }
 
 int spotfit_validate_options(const spotfit_options_t* o) {
@@ -95,6 +101,8 @@ int spotfit_validate_options(const spotfit_options_t* o) {
     return fail(SPOTFIT_E_OPTIONS, "max_pixels not in [9, 1024]");
   if (o->max_side < 3 || o->max_side > 32)
     return fail(SPOTFIT_E_OPTIONS, "max_side not in [3, 32]");
+  if (o->schedule != SPOTFIT_SCHEDULE_UNIFORM && o->schedule != SPOTFIT_SCHEDULE_MIXED)
+    return fail(SPOTFIT_E_OPTIONS, "unknown schedule");
   return SPOTFIT_OK;
 }
 
@@ -128,34 +136,95 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
       c->occupancy[i][pr] = nb > 0 ? nb : 1;
     }
   }
-  const int lanes[3] = {8, 16, 32};
-  int wpe_env = 0;
-  if (const char* env = std::getenv("SPOTFIT_GROUP_WPE")) wpe_env = std::atoi(env);
-  // register caps measured best on MI355X: 8 lanes 2, 16 lanes 3, 32 lanes 3 waves per SIMD
-  const int wpe_default[3] = {2, 3, 3};
-  for (int i = 0; i < 3; ++i) {
-    c->wpe_group[i] = (wpe_env >= 1 && wpe_env <= 4) ? wpe_env : wpe_default[i];
+  for (int pl = 0; pl < sf::group_plan_count(); ++pl) {
     int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, sf::group_kernel_symbol(lanes[i], c->wpe_group[i]), 64, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sf::group_kernel_symbol(pl), 64, 0);
     if (e != hipSuccess) {
       delete c;
       return fail_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     }
-    c->occ_group[i] = nb > 0 ? nb : 1;
+    c->occ_plan[pl] = nb > 0 ? nb : 1;
+  }
+  for (int pl = 0; pl < sf::mixed_plan_count(); ++pl) {
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sf::mixed_kernel_symbol(pl), 64, 0);
+    if (e != hipSuccess) {
+      delete c;
+      return fail_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    }
+    c->occ_mixed[pl] = nb > 0 ? nb : 1;
+  }
+  c->mixed_plan = 0;
+  if (const char* env = std::getenv("SPOTFIT_MIXED_PLAN")) {
+    const int v = std::atoi(env);
+    if (v >= 0 && v < sf::mixed_plan_count()) c->mixed_plan = v;
+  }
+  c->ws = nullptr;
+  c->ws_cap = 0;
+  // default plan per size class (measured on MI355X): <= 8 px side: 8 lanes x 1
+  // column; <= 16: 16 lanes x 1 column; <= 32: 32 lanes x 1 column
+  c->plan_for_class[0] = 0;
+  c->plan_for_class[1] = 2;
+  c->plan_for_class[2] = 4;
+  if (const char* env = std::getenv("SPOTFIT_GROUP_PLAN")) {
+    // tuning override "a,b,c": plan for each size class
+    int a = -1, b = -1, d = -1;
+    if (std::sscanf(env, "%d,%d,%d", &a, &b, &d) == 3) {
+      const int want[3] = {a, b, d};
+      const int side[3] = {8, 16, 32};
+      for (int i = 0; i < 3; ++i) {
+        int L = 0, C = 0;
+        sf::group_plan_shape(want[i], &L, &C);
+        if (L * C >= side[i]) c->plan_for_class[i] = want[i];
+      }
+    }
   }
   if (const char* env = std::getenv("SPOTFIT_WAVES_PER_CU")) {
     const int v = std::atoi(env);
     if (v > 0 && v <= 64) {
       for (int i = 0; i < 5; ++i) c->occupancy[i][0] = c->occupancy[i][1] = v;
-      for (int i = 0; i < 3; ++i) c->occ_group[i] = v;
+      for (int i = 0; i < 8; ++i) c->occ_plan[i] = v;
     }
   }
   *out = c;
   return SPOTFIT_OK;
 }
 
-void spotfit_ctx_destroy(spotfit_ctx_t* ctx) { delete ctx; }
+void spotfit_ctx_destroy(spotfit_ctx_t* ctx) {
+  if (!ctx) return;
+  if (ctx->ws) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->ws);
+    if (cur >= 0) (void)hipSetDevice(cur);
+  }
+  delete ctx;
+}
+
+int spotfit_ctx_reserve(spotfit_ctx_t* ctx, int64_t n) {
+  if (!ctx) return fail(SPOTFIT_E_NULL, "ctx_reserve: NULL context");
+  if (n < 0 || n > ((int64_t)1 << 31) - 1) return fail(SPOTFIT_E_ARG, "ctx_reserve: n not in [0, 2^31)");
+  if (n <= ctx->ws_cap) return SPOTFIT_OK;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if (cur != ctx->device && (e = hipSetDevice(ctx->device)) != hipSuccess)
+    return fail_hip(e, "hipSetDevice");
+  if (ctx->ws) {
+    e = hipDeviceSynchronize();  // a previous call may still use the old workspace
+    if (e == hipSuccess) e = hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+  }
+  int32_t* p = nullptr;
+  if (e == hipSuccess) e = hipMalloc((void**)&p, sizeof(int32_t) * (size_t)(8 + 3 * n));
+  if (cur != ctx->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return fail_hip(e, "hipMalloc (mixed workspace)");
+  ctx->ws = p;
+  ctx->ws_cap = n;
+  return SPOTFIT_OK;
+}
 
 int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                       const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
@@ -203,15 +272,27 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
   ka.opt.sigma_max_frac = o.sigma_max_frac;
 
   hipError_t e;
-  if (o.precision == SPOTFIT_PREC_FP64) {
-    const int lanes = sf::group_lanes_for_side(o.max_side);
-    const int gidx = lanes == 8 ? 0 : lanes == 16 ? 1 : 2;
+  if (o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED) {
+    if (n > ctx->ws_cap) {
+      const int rr = spotfit_ctx_reserve(ctx, n);
+      if (rr != SPOTFIT_OK) return rr;
+    }
+    sf::MixedWs ws{ctx->ws, ctx->ws + 8, ctx->ws_cap};
+    const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_mixed[ctx->mixed_plan];
+    const int64_t need = (n + 1) / 2;
+    const int grid = (int)(need < resident ? need : resident);
+    e = sf::launch_mixed(ctx->mixed_plan, ka, ws, grid, (hipStream_t)stream);
+  } else if (o.precision == SPOTFIT_PREC_FP64) {
+    const int cls = o.max_side <= 8 ? 0 : o.max_side <= 16 ? 1 : 2;
+    const int plan = ctx->plan_for_class[cls];
+    int lanes = 0, cpl = 0;
+    sf::group_plan_shape(plan, &lanes, &cpl);
     const int64_t per_wave = 64 / lanes;
     const int64_t need = (n + per_wave - 1) / per_wave;
     // persistent grid: as many one-wave workgroups as can be resident at once
-    const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_group[gidx];
+    const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_plan[plan];
     const int grid = (int)(need < resident ? need : resident);
-    e = sf::launch_group_kernel(lanes, ctx->wpe_group[gidx], ka, grid, (hipStream_t)stream);
+    e = sf::launch_group_kernel(plan, ka, grid, (hipStream_t)stream);
   } else if (o.precision == SPOTFIT_PREC_FP32_PLAIN) {
     const int threads = ((o.max_pixels + 63) / 64) * 64;
     e = sf::launch_plain_kernel(ka, threads, (hipStream_t)stream);

@@ -67,6 +67,7 @@ struct State {
   double red[16];                   // reduction results / moments
   double gd[4][5];                  // per parameter: dF, sum f df, dFG, d alpha, d beta
   double A4[14];                    // 4x4 normal matrix (elliptical) and right-hand side
+  int64_t next;                     // next spot index, broadcast from the group's first lane
 };
 
 // Totals over the group of the first K values; written to red[0..K-1].
@@ -103,40 +104,52 @@ __device__ __forceinline__ double pow10i(int k) {
   return k < 0 ? 1.0 / t : t;
 }
 
-// Cholesky solve of (A + lam diag A) d = bv, 4x4 symmetric (upper triangle in
-// A[10]: 00 01 02 03 11 12 13 22 23 33).  NaN on a non-positive pivot.
+// 1/x from the hardware reciprocal refined by two Newton steps (~1 ulp).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Solve (A + lam diag A) d = bv for the 4x4 symmetric A (upper triangle in
+// A[10]: 00 01 02 03 11 12 13 22 23 33) by an LDL^T factorisation; NaN when a
+// pivot is not positive (the matrix is not positive definite).
 __device__ __forceinline__ void solve4(const double* A, const double* bv, double lam, double* d) {
   const double m00 = A[0] + lam * A[0], m11 = A[4] + lam * A[4];
   const double m22 = A[7] + lam * A[7], m33 = A[9] + lam * A[9];
-  bool ok = m00 > 0.0;
-  const double l00 = sqrt(m00), i00 = 1.0 / l00;
-  const double l10 = A[1] * i00, l20 = A[2] * i00, l30 = A[3] * i00;
-  const double s11 = m11 - l10 * l10;
-  ok = ok && s11 > 0.0;
-  const double l11 = sqrt(s11), i11 = 1.0 / l11;
-  const double l21 = (A[5] - l20 * l10) * i11, l31 = (A[6] - l30 * l10) * i11;
-  const double s22 = m22 - l20 * l20 - l21 * l21;
-  ok = ok && s22 > 0.0;
-  const double l22 = sqrt(s22), i22 = 1.0 / l22;
-  const double l32 = (A[8] - l30 * l20 - l31 * l21) * i22;
-  const double s33 = m33 - l30 * l30 - l31 * l31 - l32 * l32;
-  ok = ok && s33 > 0.0;
-  const double l33 = sqrt(s33), i33 = 1.0 / l33;
-  const double y0 = bv[0] * i00;
-  const double y1 = (bv[1] - l10 * y0) * i11;
-  const double y2 = (bv[2] - l20 * y0 - l21 * y1) * i22;
-  const double y3 = (bv[3] - l30 * y0 - l31 * y1 - l32 * y2) * i33;
-  const double d3 = y3 * i33;
-  const double d2 = (y2 - l32 * d3) * i22;
-  const double d1 = (y1 - l21 * d2 - l31 * d3) * i11;
-  const double d0 = (y0 - l10 * d1 - l20 * d2 - l30 * d3) * i00;
-  ok = ok && __builtin_isfinite(d0) && __builtin_isfinite(d1) && __builtin_isfinite(d2) &&
-       __builtin_isfinite(d3);
+  const double d0 = m00;
+  bool ok = d0 > 0.0;
+  const double i0 = rcp_nr(d0);
+  const double l10 = A[1] * i0, l20 = A[2] * i0, l30 = A[3] * i0;
+  const double d1 = m11 - l10 * l10 * d0;
+  ok = ok && d1 > 0.0;
+  const double i1 = rcp_nr(d1);
+  const double l21 = (A[5] - l20 * l10 * d0) * i1;
+  const double l31 = (A[6] - l30 * l10 * d0) * i1;
+  const double d2 = m22 - l20 * l20 * d0 - l21 * l21 * d1;
+  ok = ok && d2 > 0.0;
+  const double i2 = rcp_nr(d2);
+  const double l32 = (A[8] - l30 * l20 * d0 - l31 * l21 * d1) * i2;
+  const double d3 = m33 - l30 * l30 * d0 - l31 * l31 * d1 - l32 * l32 * d2;
+  ok = ok && d3 > 0.0;
+  const double i3 = rcp_nr(d3);
+  const double z0 = bv[0];
+  const double z1 = bv[1] - l10 * z0;
+  const double z2 = bv[2] - l20 * z0 - l21 * z1;
+  const double z3 = bv[3] - l30 * z0 - l31 * z1 - l32 * z2;
+  const double x3 = z3 * i3;
+  const double x2 = z2 * i2 - l32 * x3;
+  const double x1 = z1 * i1 - l21 * x2 - l31 * x3;
+  const double x0 = z0 * i0 - l10 * x1 - l20 * x2 - l30 * x3;
+  ok = ok && __builtin_isfinite(x0) && __builtin_isfinite(x1) && __builtin_isfinite(x2) &&
+       __builtin_isfinite(x3);
   const double nanv = __builtin_nan("");
-  d[0] = ok ? d0 : nanv;
-  d[1] = ok ? d1 : nanv;
-  d[2] = ok ? d2 : nanv;
-  d[3] = ok ? d3 : nanv;
+  d[0] = ok ? x0 : nanv;
+  d[1] = ok ? x1 : nanv;
+  d[2] = ok ? x2 : nanv;
+  d[3] = ok ? x3 : nanv;
 }
 
 // Parameter j of (x, y, sx, sy): order of its x-moment and y-moment.
@@ -157,39 +170,44 @@ __device__ __forceinline__ int tri_j(int t) {
 //   9..12     Yq1..Yq4 = sum dy^k ey^2                    (Yq0 = sum ey^2)
 //   13, 14    B_x = sum dx ex t,  B_sx = sum dx^2 ex t    (t = sum_r g ey per column)
 //   15, 0     B_y = sum ex t_y,   B_sy = sum ex t_yy      (t_y, t_yy: (r-y), (r-y)^2 weights)
-template <int L, int WPE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_group_kernel(KArgs ka) {
-  constexpr int G = 64 / L;  // groups (spots in flight) per wavefront
-  constexpr int HM = L;      // rows held per lane
+//
+// Template parameters: L lanes per spot, CPL columns (and rows) per lane, so a
+// group holds spots with w, h <= L*CPL; WPE = minimum waves per SIMD the
+// register allocation must allow.
+template <int L, int CPL, class Src>
+__device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * CPL>* sts) {
+  constexpr int G = 64 / L;       // groups (spots in flight) per wavefront
+  constexpr int HM = L * CPL;     // largest side of a spot
   constexpr double kC0 = 0.5 * (HM - 1);  // row origin of the bilinear row moments
   constexpr int kChunk = 4;               // rows processed between scheduling barriers
-  __shared__ State<HM> sts[G];
+  static_assert(HM % kChunk == 0, "chunking");
 
   const int lane = __lane_id();
   const int gi = lane / L;
   const int li = lane % L;
   State<HM>& S = sts[gi];
-  const int64_t stride = (int64_t)gridDim.x * G;
   const KOpts o = ka.opt;
   const double tau = o.tie_tau;
 
   // ---- per-group control state (identical on the L lanes of a group) ----
-  int64_t s = (int64_t)blockIdx.x * G + gi;
+  int64_t s = src.first(gi, li, S.next);
   int w = 0, h = 0, k = 0, it = 0, status = 0, mode = kNew, n_grad = 0, n_trial = 0;
   bool sym = true;
-  // ---- per-lane data ----
-  float g[HM];  // column li of the spot (0 outside the spot)
-  double ex = 0.0, eyo = 0.0, tcol = 0.0, t1c = 0.0, t2c = 0.0;
+  // ---- per-lane data: columns li + L*j and rows li + L*j, j < CPL ----
+  float g[CPL][HM];  // the lane's columns of the spot (0 outside the spot)
+  double ex[CPL], eyo[CPL], tcol[CPL], t1c[CPL], t2c[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) ex[j] = eyo[j] = tcol[j] = t1c[j] = t2c[j] = 0.0;
 
   // Fetch the next spot of this group, writing BAD_INPUT for unusable ones.
   auto fetch = [&]() {
-    while (s < ka.n) {
+    while (s >= 0) {
       const spotfit_shape_t sh = ka.sizes[s];
       const float* in = ka.init + 4 * s;
       const float i0 = in[0], i1 = in[1], i2 = in[2], i3 = in[3];
       const int mdl = sh.model;
       const bool ell = mdl == SPOTFIT_ELL;
-      const bool bad = sh.w < 3 || sh.h < 3 || sh.w > L || sh.h > L ||
+      const bool bad = sh.w < 3 || sh.h < 3 || sh.w > HM || sh.h > HM ||
                        sh.w * sh.h > o.max_pixels || sh.w > o.max_side || sh.h > o.max_side ||
                        (mdl != SPOTFIT_SYM && !ell) || !__builtin_isfinite(i0) ||
                        !__builtin_isfinite(i1) || !__builtin_isfinite(i2) || !(i2 > 0.f) ||
@@ -208,14 +226,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         for (int r0 = 0; r0 < HM; r0 += kChunk) {
 #pragma unroll
           for (int r = r0; r < r0 + kChunk; ++r) {
-            float gv = 0.f;
-            if (r < h && li < w) {
-              gv = ka.dtype == SPOTFIT_U16
-                       ? float(static_cast<const uint16_t*>(ka.data)[off + r * w + li])
-                       : static_cast<const float*>(ka.data)[off + r * w + li];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+              const int c = li + L * j;
+              float gv = 0.f;
+              if (r < h && c < w) {
+                gv = ka.dtype == SPOTFIT_U16
+                         ? float(static_cast<const uint16_t*>(ka.data)[off + r * w + c])
+                         : static_cast<const float*>(ka.data)[off + r * w + c];
+              }
+              g[j][r] = gv;
+              cs += double(gv);
             }
-            g[r] = gv;
-            cs += double(gv);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -240,40 +262,61 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
           ka.evals_out[2 * s + 1] = 0;
         }
       }
-      s += stride;
+      s = src.next(s, li, S.next);
     }
   };
 
   fetch();
 
-  while (__builtin_amdgcn_ballot_w64(s < ka.n) != 0) {
-    if (s < ka.n) {
+  while (__builtin_amdgcn_ballot_w64(s >= 0) != 0) {
+    if (s >= 0) {
       // ================= trial evaluation at pc (Eqs. 2, 5, 6, 10) =================
       {
-        const double x = S.pc[0], y = S.pc[1], sx = S.pc[2], sy = S.pc[3];
-        const double dxc = double(li) - x;
-        const double dyr = double(li) - y;
-        ex = li < w ? exp(-0.5 * (dxc * dxc) / (sx * sx)) : 0.0;
-        eyo = li < h ? exp(-0.5 * (dyr * dyr) / (sy * sy)) : 0.0;
-        S.ey[li] = eyo;
+        const double x = S.pc[0], y = S.pc[1];
+        const double hx = -0.5 * rcp_nr(S.pc[2] * S.pc[2]);
+        const double hy = -0.5 * rcp_nr(S.pc[3] * S.pc[3]);
+        double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int c = li + L * j;
+          const double dxc = double(c) - x, dyr = double(c) - y;
+          ex[j] = c < w ? exp(dxc * dxc * hx) : 0.0;
+          eyo[j] = c < h ? exp(dyr * dyr * hy) : 0.0;
+          S.ey[c] = eyo[j];
+          v[0] += ex[j];
+          v[1] = __builtin_fma(ex[j], ex[j], v[1]);
+          v[2] += eyo[j];
+          v[3] = __builtin_fma(eyo[j], eyo[j], v[3]);
+        }
         lds_sync();
         // column sums of g ey, and the row moments needed by the derivative pass
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        double t0[CPL], t1[CPL], t2[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) t0[j] = t1[j] = t2[j] = 0.0;
 #pragma unroll
         for (int r0 = 0; r0 < HM; r0 += kChunk) {
 #pragma unroll
           for (int r = r0; r < r0 + kChunk; ++r) {
-            const double u = double(g[r]) * S.ey[r];
-            t0 += u;
-            t1 = __builtin_fma(u, double(r) - kC0, t1);
-            t2 = __builtin_fma(u, (double(r) - kC0) * (double(r) - kC0), t2);
+            const double e = S.ey[r];
+            constexpr double dummy = 0.0;
+            (void)dummy;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+              const double u = double(g[j][r]) * e;
+              t0[j] += u;
+              t1[j] = __builtin_fma(u, double(r) - kC0, t1[j]);
+              t2[j] = __builtin_fma(u, (double(r) - kC0) * (double(r) - kC0), t2[j]);
+            }
           }
           __builtin_amdgcn_sched_barrier(0);  // bounds the rows in flight (registers)
         }
-        tcol = t0;
-        t1c = t1;
-        t2c = t2;
-        double v[8] = {ex, ex * ex, eyo, eyo * eyo, ex * t0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          tcol[j] = t0[j];
+          t1c[j] = t1[j];
+          t2c[j] = t2[j];
+          v[4] = __builtin_fma(ex[j], t0[j], v[4]);
+        }
         group_sums_to<L, 8>(v, S.red, li);
         const double Sx = S.red[0], Sxx = S.red[1], Sy = S.red[2], Syy = S.red[3];
         const double FG = S.red[4];
@@ -281,22 +324,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         const double Nn = double(w * h), Gs = S.Gs;
         const double D = Nn * FF - F * F;
         const bool okD = D > 0.0 && __builtin_isfinite(D);
-        const double iD = 1.0 / D;
+        const double iD = rcp_nr(D);
         const double a = (Nn * FG - F * Gs) * iD;
         const double b = (Gs * FF - F * FG) * iD;
         // residual sum of squares, r = alpha f + beta - g over the spot's pixels
         // (the fence makes this loop re-read the row factors instead of keeping
         // all of them live in registers across the reduction)
         lds_sync();
+        double aex[CPL], bm[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          aex[j] = a * ex[j];
+          bm[j] = li + L * j < w ? b : 0.0;
+        }
         double c2 = 0.0;
-        const double bm = li < w ? b : 0.0;
 #pragma unroll
         for (int r0 = 0; r0 < HM; r0 += kChunk) {
 #pragma unroll
           for (int r = r0; r < r0 + kChunk; ++r) {
             if (r < h) {
-              const double res = __builtin_fma(a, ex * S.ey[r], bm - double(g[r]));
-              c2 = __builtin_fma(res, res, c2);
+              const double e = S.ey[r];
+#pragma unroll
+              for (int j = 0; j < CPL; ++j) {
+                const double res = __builtin_fma(aex[j], e, bm[j] - double(g[j][r]));
+                c2 = __builtin_fma(res, res, c2);
+              }
             }
           }
           __builtin_amdgcn_sched_barrier(0);
@@ -391,28 +443,47 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
       // ================= derivative pass at p (Eqs. 7-9, 11) =================
       if (do_grad) {
         const double x = S.p[0], y = S.p[1];
-        // lane li: moments of column li and row li, bilinear terms of column li
-        const double dx = double(li) - x, dy = double(li) - y;
-        const double ex2 = ex * ex, ey2 = eyo * eyo;
-        const double dx2 = dx * dx, dy2 = dy * dy;
         const double yc = y - kC0;
-        const double t1y = t1c - yc * tcol;                        // sum_r (r-y) g ey
-        const double t2y = t2c - 2.0 * yc * t1c + yc * yc * tcol;  // sum_r (r-y)^2 g ey
-        double v[16] = {ex * t2y,        dx * ex,         dx2 * ex,        dx * ex2,
-                        dx2 * ex2,       dx2 * dx * ex2,  dx2 * dx2 * ex2, dy * eyo,
-                        dy2 * eyo,       dy * ey2,        dy2 * ey2,       dy2 * dy * ey2,
-                        dy2 * dy2 * ey2, dx * ex * tcol,  dx2 * ex * tcol, ex * t1y};
+        // lane li: moments of its columns and rows, bilinear terms of its columns
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int c = li + L * j;
+          const double dx = double(c) - x, dy = double(c) - y;
+          const double ex2 = ex[j] * ex[j], ey2 = eyo[j] * eyo[j];
+          const double dx2 = dx * dx, dy2 = dy * dy;
+          const double t1y = t1c[j] - yc * tcol[j];                          // sum_r (r-y) g ey
+          const double t2y = t2c[j] - 2.0 * yc * t1c[j] + yc * yc * tcol[j];  // sum_r (r-y)^2 g ey
+          v[0] = __builtin_fma(ex[j], t2y, v[0]);
+          v[1] = __builtin_fma(dx, ex[j], v[1]);
+          v[2] = __builtin_fma(dx2, ex[j], v[2]);
+          v[3] = __builtin_fma(dx, ex2, v[3]);
+          v[4] = __builtin_fma(dx2, ex2, v[4]);
+          v[5] = __builtin_fma(dx2 * dx, ex2, v[5]);
+          v[6] = __builtin_fma(dx2 * dx2, ex2, v[6]);
+          v[7] = __builtin_fma(dy, eyo[j], v[7]);
+          v[8] = __builtin_fma(dy2, eyo[j], v[8]);
+          v[9] = __builtin_fma(dy, ey2, v[9]);
+          v[10] = __builtin_fma(dy2, ey2, v[10]);
+          v[11] = __builtin_fma(dy2 * dy, ey2, v[11]);
+          v[12] = __builtin_fma(dy2 * dy2, ey2, v[12]);
+          v[13] = __builtin_fma(dx * ex[j], tcol[j], v[13]);
+          v[14] = __builtin_fma(dx2 * ex[j], tcol[j], v[14]);
+          v[15] = __builtin_fma(ex[j], t1y, v[15]);
+        }
         group_sums_to<L, 16>(v, S.red, li);
-        const double isx = 1.0 / S.p[2], isy = 1.0 / S.p[3];
+        const double isx = rcp_nr(S.p[2]), isy = rcp_nr(S.p[3]);
         const double Sx = S.Sx, Sy = S.Sy, Sxx = S.Sxx, Syy = S.Syy;
-        const double Nn = double(w * h), Gs = S.Gs, iD = 1.0 / S.D;
+        const double Nn = double(w * h), Gs = S.Gs, iD = rcp_nr(S.D);
         const double F = S.F, FF = S.FF, FG = S.FG, a = S.a, b = S.b;
+        const double w0 = isx * isx, w1 = isy * isy, w2 = w0 * isx, w3 = w1 * isy;
         // --- lanes j < 4: sums of parameter j (Eq. 7) and Eq. 8 ---
         if (li < 4) {
           const int j = li;
           const int ox = ox_of(j), oy = oy_of(j);
-          const double wj = j == 0 ? isx * isx : j == 1 ? isy * isy : j == 2 ? isx * isx * isx
-                                                                             : isy * isy * isy;
+          const double wj = j == 0 ? w0 : j == 1 ? w1 : j == 2 ? w2 : w3;
           const double X = ox == 0 ? Sx : S.red[ox];
           const double Y = oy == 0 ? Sy : S.red[6 + oy];
           const double Xq = ox == 0 ? Sxx : S.red[2 + ox];
@@ -440,10 +511,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
             const int oxs = ox_of(i) + ox_of(j), oys = oy_of(i) + oy_of(j);
             const double Xq = oxs == 0 ? Sxx : S.red[2 + oxs];
             const double Yq = oys == 0 ? Syy : S.red[8 + oys];
-            const double wi = i == 0 ? isx * isx : i == 1 ? isy * isy : i == 2 ? isx * isx * isx
-                                                                               : isy * isy * isy;
-            const double wj = j == 0 ? isx * isx : j == 1 ? isy * isy : j == 2 ? isx * isx * isx
-                                                                               : isy * isy * isy;
+            const double wi = i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : w3;
+            const double wj = j == 0 ? w0 : j == 1 ? w1 : j == 2 ? w2 : w3;
             const double Sdd = Xq * Yq * wi * wj;  // sum df_i df_j
             val = dai * daj * FF + a * (dai * S.gd[j][1] + daj * S.gd[i][1]) +
                   (dai * dbj + dbi * daj) * F + a * a * Sdd +
@@ -507,61 +576,228 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
             ka.evals_out[2 * s + 1] = n_trial;
           }
         }
-        s += stride;
+        s = src.next(s, li, S.next);
         fetch();
       }
     }
   }
 }
 
-template <int L, int WPE>
+// Spots s = first, first + stride, ... of a uniform batch (static striding).
+struct StridedSrc {
+  int64_t n, base, stride;
+  __device__ int64_t first(int gi, int, int64_t&) const {
+    const int64_t s = base + gi;
+    return s < n ? s : -1;
+  }
+  __device__ int64_t next(int64_t s, int, int64_t&) const {
+    s += stride;
+    return s < n ? s : -1;
+  }
+};
+
+template <int L, int CPL, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_group_kernel(KArgs ka) {
+  constexpr int G = 64 / L;
+  __shared__ State<L * CPL> sts[G];
+  StridedSrc src{ka.n, (int64_t)blockIdx.x * G, (int64_t)gridDim.x * G};
+  fit_groups<L, CPL>(ka, src, sts);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batches of uneven spot sizes: one persistent launch.
+//
+// A classify pass buckets the spot indices by size class (largest side <= 8,
+// <= 16, <= 32) into per-class lists; the fit kernel then lets every wavefront
+// run the plan (lanes per spot, columns per lane) of one class, its groups
+// taking spots from that class's list through an atomic counter.  A wavefront
+// whose class runs dry moves on to the next class, so no class waits for
+// another's tail.  Result order is by spot index, independent of scheduling.
+// ---------------------------------------------------------------------------
+struct QueueSrc {
+  const int32_t* list;  // spot indices of the class
+  int32_t* take;        // next position to take (atomic)
+  int32_t count;        // spots in the class
+  __device__ int64_t pull(int li, int64_t& slot) const {
+    if (li == 0) {
+      const int32_t v = atomicAdd(take, 1);
+      slot = v < count ? (int64_t)list[v] : -1;
+    }
+    lds_sync();
+    const int64_t r = slot;
+    lds_sync();
+    return r;
+  }
+  __device__ int64_t first(int, int li, int64_t& slot) const { return pull(li, slot); }
+  __device__ int64_t next(int64_t, int li, int64_t& slot) const { return pull(li, slot); }
+};
+
+__device__ __forceinline__ int size_class(const spotfit_shape_t& sh) {
+  const int m = sh.w > sh.h ? sh.w : sh.h;
+  return m <= 8 ? 0 : m <= 16 ? 1 : 2;
+}
+
+__global__ void mixed_reset_kernel(MixedWs ws) {
+  if (threadIdx.x < 8) ws.counters[threadIdx.x] = 0;
+}
+
+// Small batches (serving frames): zero the counters and classify in one
+// workgroup, one launch instead of two.
+__global__ __launch_bounds__(1024) void mixed_small_classify_kernel(const spotfit_shape_t* sizes,
+                                                                    int64_t n, MixedWs ws) {
+  if (threadIdx.x < 8) ws.counters[threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = __lane_id();
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t b = 0; b < n; b += blockDim.x) {
+    const int64_t s = b + threadIdx.x;
+    const int cls = s < n ? size_class(sizes[s]) : -1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const uint64_t mask = __builtin_amdgcn_ballot_w64(cls == c);
+      if (mask == 0) continue;
+      const int leader = __builtin_ctzll(mask);
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&ws.counters[c], (int)__builtin_popcountll(mask));
+      base = __builtin_amdgcn_readlane(base, leader);
+      if (cls == c) ws.lists[(int64_t)c * ws.cap + base + __builtin_popcountll(mask & below)] = (int32_t)s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void mixed_classify_kernel(const spotfit_shape_t* sizes, int64_t n,
+                                                             MixedWs ws) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int cls = s < n ? size_class(sizes[s]) : -1;
+  const int lane = __lane_id();
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(cls == c);
+    if (mask == 0) continue;
+    const int leader = __builtin_ctzll(mask);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&ws.counters[c], (int)__builtin_popcountll(mask));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if (cls == c) ws.lists[(int64_t)c * ws.cap + base + __builtin_popcountll(mask & below)] = (int32_t)s;
+  }
+}
+
+template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_mixed_kernel(
+    KArgs ka, MixedWs ws) {
+  __shared__ union {
+    State<L0 * C0> a[64 / L0];
+    State<L1 * C1> b[64 / L1];
+    State<L2 * C2> c[64 / L2];
+  } st;
+  // counters[0..2]: spots per class (filled by the classify pass), [3..5]: taken
+  const int start = blockIdx.x % 3;
+  for (int q = 0; q < 3; ++q) {
+    const int c = (start + q) % 3;
+    QueueSrc src{ws.lists + (int64_t)c * ws.cap, ws.counters + 3 + c, ws.counters[c]};
+    if (c == 0)
+      fit_groups<L0, C0>(ka, src, st.a);
+    else if (c == 1)
+      fit_groups<L1, C1>(ka, src, st.b);
+    else
+      fit_groups<L2, C2>(ka, src, st.c);
+  }
+}
+
+template <int L, int CPL, int WPE>
 static hipError_t launch_lw(const KArgs& ka, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((fit_group_kernel<L, WPE>), dim3(grid), dim3(64), 0, st, ka);
+  hipLaunchKernelGGL((fit_group_kernel<L, CPL, WPE>), dim3(grid), dim3(64), 0, st, ka);
   return hipGetLastError();
 }
 
-template <int L>
-static hipError_t launch_l(int wpe, const KArgs& ka, int grid, hipStream_t st) {
-  switch (wpe) {
-    case 2: return launch_lw<L, 2>(ka, grid, st);
-    case 3: return launch_lw<L, 3>(ka, grid, st);
-    case 4: return launch_lw<L, 4>(ka, grid, st);
-    default: return launch_lw<L, 1>(ka, grid, st);
-  }
+template <int L, int CPL, int WPE>
+static const void* sym_lw() {
+  return reinterpret_cast<const void*>(&fit_group_kernel<L, CPL, WPE>);
 }
 
-template <int L>
-static const void* symbol_l(int wpe) {
-  switch (wpe) {
-    case 2: return reinterpret_cast<const void*>(&fit_group_kernel<L, 2>);
-    case 3: return reinterpret_cast<const void*>(&fit_group_kernel<L, 3>);
-    case 4: return reinterpret_cast<const void*>(&fit_group_kernel<L, 4>);
-    default: return reinterpret_cast<const void*>(&fit_group_kernel<L, 1>);
-  }
-}
+// The compiled plans: (lanes per spot, columns per lane, min waves per SIMD).
+#define SF_GROUP_PLANS(X) \
+  X(0, 8, 1, 2)           \
+  X(1, 8, 2, 2)           \
+  X(2, 16, 1, 3)          \
+  X(3, 16, 2, 2)          \
+  X(4, 32, 1, 3)
 
 }  // namespace grp
 
-int group_lanes_for_side(int max_side) {
-  if (max_side <= 8) return 8;
-  if (max_side <= 16) return 16;
-  return 32;
+int group_plan_count() { return 5; }
+
+void group_plan_shape(int plan, int* lanes, int* cpl) {
+#define SF_SHAPE(I, L, C, W) \
+  if (plan == I) {           \
+    *lanes = L;              \
+    *cpl = C;                \
+    return;                  \
+  }
+  SF_GROUP_PLANS(SF_SHAPE)
+#undef SF_SHAPE
+  *lanes = 0;
+  *cpl = 0;
 }
 
-const void* group_kernel_symbol(int lanes, int wpe) {
-  switch (lanes) {
-    case 8: return grp::symbol_l<8>(wpe);
-    case 16: return grp::symbol_l<16>(wpe);
-    default: return grp::symbol_l<32>(wpe);
-  }
+const void* group_kernel_symbol(int plan) {
+#define SF_SYM(I, L, C, W) \
+  if (plan == I) return grp::sym_lw<L, C, W>();
+  SF_GROUP_PLANS(SF_SYM)
+#undef SF_SYM
+  return nullptr;
 }
 
-hipError_t launch_group_kernel(int lanes, int wpe, const KArgs& ka, int grid, hipStream_t st) {
-  switch (lanes) {
-    case 8: return grp::launch_l<8>(wpe, ka, grid, st);
-    case 16: return grp::launch_l<16>(wpe, ka, grid, st);
-    default: return grp::launch_l<32>(wpe, ka, grid, st);
+hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t st) {
+#define SF_LAUNCH(I, L, C, W) \
+  if (plan == I) return grp::launch_lw<L, C, W>(ka, grid, st);
+  SF_GROUP_PLANS(SF_LAUNCH)
+#undef SF_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+// Mixed-size plans: plans of the classes (<= 8, <= 16, <= 32 px side).
+#define SF_MIXED_PLANS(X)       \
+  X(0, 8, 1, 16, 1, 32, 1, 3)   \
+  X(1, 8, 1, 8, 2, 32, 1, 2)    \
+  X(2, 8, 1, 16, 1, 16, 2, 2)
+
+int mixed_plan_count() { return 3; }
+
+const void* mixed_kernel_symbol(int plan) {
+#define SF_MSYM(I, A, B, C, D, E, F, W) \
+  if (plan == I) return reinterpret_cast<const void*>(&grp::fit_mixed_kernel<A, B, C, D, E, F, W>);
+  SF_MIXED_PLANS(SF_MSYM)
+#undef SF_MSYM
+  return nullptr;
+}
+
+hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, hipStream_t st) {
+  hipError_t e;
+  if (ka.n <= 65536) {
+    hipLaunchKernelGGL(grp::mixed_small_classify_kernel, dim3(1), dim3(1024), 0, st, ka.sizes, ka.n, ws);
+    e = hipGetLastError();
+  } else {
+    hipLaunchKernelGGL(grp::mixed_reset_kernel, dim3(1), dim3(64), 0, st, ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t cb = (ka.n + 255) / 256;
+    hipLaunchKernelGGL(grp::mixed_classify_kernel, dim3((unsigned)cb), dim3(256), 0, st, ka.sizes,
+                       ka.n, ws);
+    e = hipGetLastError();
   }
+  if (e != hipSuccess) return e;
+#define SF_MLAUNCH(I, A, B, C, D, E, F, W)                                                   \
+  if (plan == I) {                                                                           \
+    hipLaunchKernelGGL((grp::fit_mixed_kernel<A, B, C, D, E, F, W>), dim3(grid), dim3(64), 0, \
+                       st, ka, ws);                                                          \
+    return hipGetLastError();                                                                \
+  }
+  SF_MIXED_PLANS(SF_MLAUNCH)
+#undef SF_MLAUNCH
+  return hipErrorInvalidValue;
 }
 
 }  // namespace sf

@@ -49,10 +49,24 @@ hipError_t launch_wave_kernel(int ppl, int precision, const KArgs& ka, int grid,
 // One workgroup per spot with `threads` threads (a multiple of 64, >= max_pixels).
 hipError_t launch_plain_kernel(const KArgs& ka, int threads, hipStream_t st);
 
-// Lanes per spot of the separable kernel able to hold spots with w, h <= max_side.
-int group_lanes_for_side(int max_side);
-// wpe: minimum waves per SIMD the register allocation must allow (1..4).
-const void* group_kernel_symbol(int lanes, int wpe);
-hipError_t launch_group_kernel(int lanes, int wpe, const KArgs& ka, int grid, hipStream_t st);
+// Device workspace of mixed-size batches: counters[0..2] spots per size class,
+// counters[3..5] spots taken; lists: 3 regions of `cap` spot indices.
+struct MixedWs {
+  int32_t* counters;
+  int32_t* lists;
+  int64_t cap;
+};
+
+// Mixed-size batches: reset + classify + one persistent fit launch.
+int mixed_plan_count();
+const void* mixed_kernel_symbol(int plan);
+hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, hipStream_t st);
+
+// Plans of the separable kernel: plan p groups `lanes` lanes per spot with `cpl`
+// columns per lane and holds spots with w, h <= lanes * cpl.
+int group_plan_count();
+void group_plan_shape(int plan, int* lanes, int* cpl);
+const void* group_kernel_symbol(int plan);
+hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t st);
 
 }  // namespace sf

@@ -1,0 +1,557 @@
+// spotfit_serve.hip -- real-time serving loop for camera frames of fiducial
+// spots (the paper's use: tracking markers at hundreds to thousands of frames
+// per second for sample stabilisation, Introduction).
+//
+// A frame is submitted from host memory and copied into pinned staging rings;
+// it is admitted only if the device-memory budget (pixel ring + per-spot ring)
+// and a frame slot have room, otherwise submit returns SPOTFIT_E_AGAIN.  A
+// dispatcher thread continuously folds every admitted frame into the next
+// launch (continuous batching): copy in, fit, copy out on one of several
+// streams, each with its own context, so batches overlap on the device.  When a
+// batch's event completes its results are copied to the callers' host arrays
+// and the frames' ring space is released (oldest first).  Latency is measured
+// from the frame's arrival (submit time, or the scheduled arrival in replay) to
+// the moment its results are in the caller's arrays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "spotfit.h"
+#include "spotfit_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+inline uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             Clock::now().time_since_epoch())
+      .count();
+}
+
+enum FrameState : int { kFree = 0, kAdmitted = 1, kLaunched = 2, kDone = 3, kFailed = 4 };
+
+struct FrameRec {
+  uint64_t ticket = 0;
+  int state = kFree;
+  int dtype = 0;
+  int64_t n = 0;           // spots
+  int64_t spot0 = 0;       // first index in the spot ring
+  int64_t pix_off = 0;     // byte offset in the pixel ring
+  int64_t pix_bytes = 0;   // bytes reserved in the pixel ring (incl. skipped tail)
+  int64_t pix_alloc = 0;   // aligned bytes of the frame's own pixels
+  int64_t spot_res = 0;    // spots reserved in the spot ring (incl. skipped tail)
+  uint64_t t_arrival = 0;  // ns
+  uint64_t t_done = 0;
+  float* params = nullptr;
+  float* chi2 = nullptr;
+  int32_t* iters = nullptr;
+  int32_t* status = nullptr;
+};
+
+struct Batch {
+  int stream = 0;
+  hipEvent_t ev = nullptr;
+  uint64_t first_ticket = 0;  // frames [first_ticket, first_ticket + n_frames)
+  int n_frames = 0;
+  int64_t spot0 = 0, n_spots = 0;
+  bool failed = false;
+};
+
+}  // namespace
+
+struct spotfit_serve {
+  int device = 0;
+  spotfit_options_t opt{};
+  int n_streams = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<spotfit_ctx_t*> ctxs;
+  std::vector<bool> stream_busy;
+
+  // rings: pixels (bytes) and per-spot records, device and pinned host mirrors
+  int64_t pix_cap = 0, spot_cap = 0;
+  unsigned char* d_pix = nullptr;
+  unsigned char* h_pix = nullptr;
+  spotfit_shape_t *d_sizes = nullptr, *h_sizes = nullptr;
+  int64_t *d_offs = nullptr, *h_offs = nullptr;
+  float *d_init = nullptr, *h_init = nullptr;
+  float *d_params = nullptr, *h_params = nullptr;
+  float *d_chi2 = nullptr, *h_chi2 = nullptr;
+  int32_t *d_iters = nullptr, *h_iters = nullptr;
+  int32_t *d_status = nullptr, *h_status = nullptr;
+  int64_t pix_head = 0, pix_used = 0, spot_head = 0, spot_used = 0;
+
+  // frame slots, FIFO by ticket
+  int max_frames = 0;
+  std::vector<FrameRec> frames;
+  uint64_t next_ticket = 1;   // next ticket to hand out
+  uint64_t oldest_ticket = 1; // oldest ticket still holding ring space
+  uint64_t next_launch = 1;   // oldest admitted ticket not yet launched
+
+  std::deque<Batch> inflight;
+  std::vector<hipEvent_t> event_pool;  // completion events, reused
+  std::mutex mu;
+  std::condition_variable cv_done;
+  std::thread worker;
+  std::atomic<bool> stop{false};
+  // tickets below this are admitted: the dispatcher polls it without the lock
+  std::atomic<uint64_t> admitted_end{1};
+
+  // statistics
+  std::vector<uint64_t> lat_ns;
+  uint64_t frames_done = 0, spots_done = 0, batches = 0, rejected = 0, frames_failed = 0;
+  uint64_t t_first = 0, t_last = 0;
+  std::string error;
+
+  FrameRec& rec(uint64_t t) { return frames[t % (uint64_t)max_frames]; }
+  void run();
+  bool launch_ready();
+  bool reap();
+};
+
+namespace {
+
+thread_local std::string g_serve_error;
+
+int serve_fail(int code, const std::string& what) {
+  g_serve_error = what;
+  return code;
+}
+
+template <typename T>
+hipError_t alloc_pair(T** d, T** h, int64_t n) {
+  hipError_t e = hipMalloc((void**)d, sizeof(T) * (size_t)n);
+  if (e != hipSuccess) return e;
+  return hipHostMalloc((void**)h, sizeof(T) * (size_t)n, hipHostMallocDefault);
+}
+
+template <typename T>
+void free_pair(T* d, T* h) {
+  if (d) (void)hipFree(d);
+  if (h) (void)hipHostFree(h);
+}
+
+}  // namespace
+
+// Launch one batch of the oldest admitted frames on a free stream.  Returns true
+// if something was launched.
+bool spotfit_serve::launch_ready() {
+  int si = -1;
+  uint64_t t0, t1;
+  int64_t spot0, nsp = 0;
+  int dtype;
+  // nothing new to launch, or no stream free: return without taking the lock
+  if (next_launch >= admitted_end.load(std::memory_order_acquire)) return false;
+  {
+    bool any_free = false;
+    for (int i = 0; i < n_streams; ++i) any_free = any_free || !stream_busy[i];
+    if (!any_free) return false;
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    while (next_launch < next_ticket && rec(next_launch).state == kDone) ++next_launch;
+    if (next_launch >= next_ticket) return false;
+    FrameRec& f0 = rec(next_launch);
+    if (f0.state != kAdmitted) return false;
+    for (int i = 0; i < n_streams; ++i)
+      if (!stream_busy[i]) {
+        si = i;
+        break;
+      }
+    if (si < 0) return false;
+    // the batch: consecutive admitted frames of one dtype that are contiguous in
+    // the spot ring
+    t0 = next_launch;
+    spot0 = f0.spot0;
+    dtype = f0.dtype;
+    t1 = t0;
+    while (t1 < next_ticket) {
+      FrameRec& f = rec(t1);
+      if (f.state != kAdmitted || f.dtype != dtype || f.spot0 != spot0 + nsp) break;
+      nsp += f.n;
+      ++t1;
+    }
+    for (uint64_t t = t0; t < t1; ++t) rec(t).state = kLaunched;
+    next_launch = t1;
+    stream_busy[si] = true;
+  }
+  hipStream_t st = streams[si];
+  // pixel bytes of the batch: frames are consecutive in the pixel ring except
+  // where it wrapped, so copy maximal contiguous runs
+  hipError_t e = hipSuccess;
+  {
+    int64_t run0 = -1, run1 = -1;
+    for (uint64_t t = t0; t <= t1 && e == hipSuccess; ++t) {
+      const bool last = t == t1;
+      if (!last) {
+        const FrameRec& f = rec(t);
+        if (run0 >= 0 && f.pix_off == run1) {
+          run1 = f.pix_off + f.pix_alloc;
+          continue;
+        }
+      }
+      if (run0 >= 0)
+        e = hipMemcpyAsync(d_pix + run0, h_pix + run0, (size_t)(run1 - run0), hipMemcpyHostToDevice, st);
+      if (!last) {
+        const FrameRec& f = rec(t);
+        run0 = f.pix_off;
+        run1 = f.pix_off + f.pix_alloc;
+      }
+    }
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_sizes + spot0, h_sizes + spot0, sizeof(spotfit_shape_t) * nsp,
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_offs + spot0, h_offs + spot0, sizeof(int64_t) * nsp, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_init + 4 * spot0, h_init + 4 * spot0, sizeof(float) * 4 * nsp,
+                       hipMemcpyHostToDevice, st);
+  int rc = SPOTFIT_OK;
+  if (e == hipSuccess)
+    rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0, d_init + 4 * spot0,
+                           nsp, &opt, d_params + 6 * spot0, d_chi2 + spot0, d_iters + spot0,
+                           d_status + spot0, nullptr, st);
+  if (e == hipSuccess && rc == SPOTFIT_OK)
+    e = hipMemcpyAsync(h_params + 6 * spot0, d_params + 6 * spot0, sizeof(float) * 6 * nsp,
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && rc == SPOTFIT_OK)
+    e = hipMemcpyAsync(h_chi2 + spot0, d_chi2 + spot0, sizeof(float) * nsp, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && rc == SPOTFIT_OK)
+    e = hipMemcpyAsync(h_iters + spot0, d_iters + spot0, sizeof(int32_t) * nsp, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && rc == SPOTFIT_OK)
+    e = hipMemcpyAsync(h_status + spot0, d_status + spot0, sizeof(int32_t) * nsp, hipMemcpyDeviceToHost, st);
+  Batch b;
+  b.stream = si;
+  b.first_ticket = t0;
+  b.n_frames = (int)(t1 - t0);
+  b.spot0 = spot0;
+  b.n_spots = nsp;
+  b.failed = !(e == hipSuccess && rc == SPOTFIT_OK);
+  if (!b.failed) {
+    if (!event_pool.empty()) {
+      b.ev = event_pool.back();
+      event_pool.pop_back();
+      e = hipSuccess;
+    } else {
+      e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b.ev, st);
+    b.failed = e != hipSuccess;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (b.failed && error.empty())
+    error = std::string("serve batch failed: ") + (rc != SPOTFIT_OK ? spotfit_last_error() : hipGetErrorString(e));
+  inflight.push_back(b);
+  ++batches;
+  return true;
+}
+
+// Complete finished batches: copy results out, release ring space.
+bool spotfit_serve::reap() {
+  bool any = false;
+  for (auto it = inflight.begin(); it != inflight.end();) {
+    Batch& b = *it;
+    bool done = b.failed;
+    if (!done) {
+      const hipError_t q = hipEventQuery(b.ev);
+      if (q == hipErrorNotReady) {
+        ++it;
+        continue;
+      }
+      if (q != hipSuccess) b.failed = true;
+      done = true;
+      if (!b.failed) (void)hipEventSynchronize(b.ev);
+    }
+    if (b.ev) event_pool.push_back(b.ev);
+    const uint64_t tnow = now_ns();
+    std::lock_guard<std::mutex> lk(mu);
+    for (int k = 0; k < b.n_frames; ++k) {
+      FrameRec& f = rec(b.first_ticket + k);
+      if (!b.failed) {
+        std::memcpy(f.params, h_params + 6 * f.spot0, sizeof(float) * 6 * f.n);
+        std::memcpy(f.chi2, h_chi2 + f.spot0, sizeof(float) * f.n);
+        if (f.iters) std::memcpy(f.iters, h_iters + f.spot0, sizeof(int32_t) * f.n);
+        if (f.status) std::memcpy(f.status, h_status + f.spot0, sizeof(int32_t) * f.n);
+        f.state = kDone;
+        ++frames_done;
+        spots_done += (uint64_t)f.n;
+      } else {
+        f.state = kFailed;
+        ++frames_failed;
+      }
+      f.t_done = tnow;
+      lat_ns.push_back(tnow > f.t_arrival ? tnow - f.t_arrival : 0);
+    }
+    t_last = tnow;
+    stream_busy[b.stream] = false;
+    // release ring space of the oldest finished frames
+    while (oldest_ticket < next_ticket) {
+      FrameRec& f = rec(oldest_ticket);
+      if (f.state != kDone && f.state != kFailed) break;
+      pix_used -= f.pix_bytes;
+      spot_used -= f.spot_res;
+      ++oldest_ticket;
+    }
+    it = inflight.erase(it);
+    any = true;
+  }
+  if (any) cv_done.notify_all();
+  return any;
+}
+
+void spotfit_serve::run() {
+  (void)hipSetDevice(device);
+  while (!stop.load(std::memory_order_acquire)) {
+    bool busy = inflight.empty() ? false : reap();
+    busy = launch_ready() || busy;
+    if (!busy) __builtin_ia32_pause();
+  }
+  // drain: wait for everything launched
+  for (auto& b : inflight)
+    if (b.ev) (void)hipEventSynchronize(b.ev);
+  reap();
+}
+
+extern "C" {
+
+int spotfit_serve_create(spotfit_serve_t** out, int device, const spotfit_options_t* opt,
+                         size_t budget, int32_t max_frames, int32_t n_streams) {
+  if (!out) return serve_fail(SPOTFIT_E_NULL, "serve_create: NULL out pointer");
+  *out = nullptr;
+  if (max_frames < 1 || max_frames > (1 << 20) || n_streams < 1 || n_streams > 16 ||
+      budget < ((size_t)1 << 20))
+    return serve_fail(SPOTFIT_E_ARG, "serve_create: max_frames in [1, 2^20], n_streams in [1, 16], budget >= 1 MiB");
+  spotfit_options_t o;
+  if (opt)
+    o = *opt;
+  else
+    spotfit_default_options(&o);
+  int rc = spotfit_validate_options(&o);
+  if (rc != SPOTFIT_OK) return serve_fail(rc, spotfit_last_error());
+  spotfit_serve* sv = new (std::nothrow) spotfit_serve();
+  if (!sv) return serve_fail(SPOTFIT_E_ARG, "serve_create: out of host memory");
+  sv->device = device;
+  sv->opt = o;
+  sv->n_streams = n_streams;
+  sv->max_frames = max_frames;
+  sv->frames.resize((size_t)max_frames);
+  // budget split: 3/4 pixels, 1/4 per-spot records (28 B in + 36 B out)
+  sv->pix_cap = (int64_t)(budget / 4 * 3) & ~(int64_t)255;
+  sv->spot_cap = (int64_t)(budget / 4) / 64;
+  hipError_t e = hipSetDevice(device);
+  auto cleanup = [&](hipError_t err, const char* where) {
+    spotfit_serve_destroy(sv);
+    return serve_fail(SPOTFIT_E_HIP, std::string(where) + ": " + hipGetErrorString(err));
+  };
+  if (e != hipSuccess) return cleanup(e, "hipSetDevice");
+  if ((e = alloc_pair(&sv->d_pix, &sv->h_pix, sv->pix_cap)) != hipSuccess) return cleanup(e, "pixel ring");
+  if ((e = alloc_pair(&sv->d_sizes, &sv->h_sizes, sv->spot_cap)) != hipSuccess) return cleanup(e, "sizes ring");
+  if ((e = alloc_pair(&sv->d_offs, &sv->h_offs, sv->spot_cap)) != hipSuccess) return cleanup(e, "offsets ring");
+  if ((e = alloc_pair(&sv->d_init, &sv->h_init, 4 * sv->spot_cap)) != hipSuccess) return cleanup(e, "init ring");
+  if ((e = alloc_pair(&sv->d_params, &sv->h_params, 6 * sv->spot_cap)) != hipSuccess) return cleanup(e, "params ring");
+  if ((e = alloc_pair(&sv->d_chi2, &sv->h_chi2, sv->spot_cap)) != hipSuccess) return cleanup(e, "chi2 ring");
+  if ((e = alloc_pair(&sv->d_iters, &sv->h_iters, sv->spot_cap)) != hipSuccess) return cleanup(e, "iters ring");
+  if ((e = alloc_pair(&sv->d_status, &sv->h_status, sv->spot_cap)) != hipSuccess) return cleanup(e, "status ring");
+  for (int i = 0; i < n_streams; ++i) {
+    hipStream_t st = nullptr;
+    if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return cleanup(e, "stream");
+    sv->streams.push_back(st);
+    spotfit_ctx_t* c = nullptr;
+    rc = spotfit_ctx_create(&c, device);
+    if (rc != SPOTFIT_OK) {
+      std::string m = spotfit_last_error();
+      spotfit_serve_destroy(sv);
+      return serve_fail(rc, m);
+    }
+    sv->ctxs.push_back(c);
+    if (o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED) {
+      rc = spotfit_ctx_reserve(c, sv->spot_cap);
+      if (rc != SPOTFIT_OK) {
+        std::string m = spotfit_last_error();
+        spotfit_serve_destroy(sv);
+        return serve_fail(rc, m);
+      }
+    }
+  }
+  sv->stream_busy.assign((size_t)n_streams, false);
+  sv->lat_ns.reserve(1 << 16);
+  sv->worker = std::thread([sv] { sv->run(); });
+  *out = sv;
+  return SPOTFIT_OK;
+}
+
+int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_t arrival_ns,
+                         uint64_t* ticket) {
+  if (!sv || !fr || !ticket) return serve_fail(SPOTFIT_E_NULL, "serve_submit: NULL argument");
+  if (fr->n_spots < 0 || (fr->n_spots > 0 && (!fr->data || !fr->sizes || !fr->init || !fr->params_out ||
+                                               !fr->chi2_out)))
+    return serve_fail(SPOTFIT_E_ARG, "serve_submit: bad frame");
+  if (fr->dtype != SPOTFIT_U16 && fr->dtype != SPOTFIT_F32) return serve_fail(SPOTFIT_E_ARG, "serve_submit: dtype");
+  const int64_t n = fr->n_spots;
+  const int64_t esz = fr->dtype == SPOTFIT_U16 ? 2 : 4;
+  int64_t npx = 0;
+  for (int64_t i = 0; i < n; ++i) npx += (int64_t)fr->sizes[i].w * fr->sizes[i].h;
+  const int64_t bytes = ((npx * esz) + 255) & ~(int64_t)255;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  const uint64_t t = sv->next_ticket;
+  // a free slot, and room in both rings (skipping a ring's tail when the frame
+  // does not fit before the wrap)
+  const bool slot_ok = t - sv->oldest_ticket < (uint64_t)sv->max_frames;
+  int64_t pix_skip = sv->pix_cap - sv->pix_head < bytes ? sv->pix_cap - sv->pix_head : 0;
+  int64_t spot_skip = sv->spot_cap - sv->spot_head < n ? sv->spot_cap - sv->spot_head : 0;
+  const bool pix_ok = bytes <= sv->pix_cap && sv->pix_used + pix_skip + bytes <= sv->pix_cap;
+  const bool spot_ok = n <= sv->spot_cap && sv->spot_used + spot_skip + n <= sv->spot_cap;
+  if (!slot_ok || !pix_ok || !spot_ok) {
+    ++sv->rejected;
+    return SPOTFIT_E_AGAIN;
+  }
+  if (pix_skip) sv->pix_head = 0;
+  if (spot_skip) sv->spot_head = 0;
+  FrameRec& f = sv->rec(t);
+  f = FrameRec();
+  f.ticket = t;
+  f.dtype = fr->dtype;
+  f.n = n;
+  f.spot0 = sv->spot_head;
+  f.pix_off = sv->pix_head;
+  f.pix_bytes = bytes + pix_skip;
+  f.pix_alloc = bytes;
+  f.spot_res = n + spot_skip;
+  f.t_arrival = arrival_ns ? arrival_ns : now_ns();
+  f.params = fr->params_out;
+  f.chi2 = fr->chi2_out;
+  f.iters = fr->iters_out;
+  f.status = fr->status_out;
+  sv->pix_head = (sv->pix_head + bytes) % sv->pix_cap;
+  sv->spot_head = (sv->spot_head + n) % sv->spot_cap;
+  sv->pix_used += f.pix_bytes;
+  sv->spot_used += f.spot_res;
+  // stage the frame (pinned mirrors); element offsets into the pixel ring
+  std::memcpy(sv->h_pix + f.pix_off, fr->data, (size_t)(npx * esz));
+  std::memcpy(sv->h_sizes + f.spot0, fr->sizes, sizeof(spotfit_shape_t) * n);
+  std::memcpy(sv->h_init + 4 * f.spot0, fr->init, sizeof(float) * 4 * n);
+  int64_t o = f.pix_off / esz;
+  for (int64_t i = 0; i < n; ++i) {
+    sv->h_offs[f.spot0 + i] = o;
+    o += (int64_t)fr->sizes[i].w * fr->sizes[i].h;
+  }
+  if (sv->t_first == 0) sv->t_first = f.t_arrival;
+  sv->next_ticket = t + 1;
+  f.state = n > 0 ? kAdmitted : kDone;
+  sv->admitted_end.store(t + 1, std::memory_order_release);
+  if (n == 0) {
+    // nothing to fit: complete at once (keeps FIFO order of tickets)
+    f.t_done = now_ns();
+    ++sv->frames_done;
+  }
+  *ticket = t;
+  return SPOTFIT_OK;
+}
+
+int spotfit_serve_poll(spotfit_serve_t* sv, uint64_t ticket) {
+  if (!sv) return serve_fail(SPOTFIT_E_NULL, "serve_poll: NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (ticket == 0 || ticket >= sv->next_ticket) return serve_fail(SPOTFIT_E_ARG, "serve_poll: unknown ticket");
+  if (ticket < sv->oldest_ticket) return SPOTFIT_OK;  // finished and released
+  const FrameRec& f = sv->rec(ticket);
+  if (f.state == kDone) return SPOTFIT_OK;
+  if (f.state == kFailed) return serve_fail(SPOTFIT_E_HIP, sv->error);
+  return 1;
+}
+
+int spotfit_serve_wait(spotfit_serve_t* sv, uint64_t ticket) {
+  if (!sv) return serve_fail(SPOTFIT_E_NULL, "serve_wait: NULL");
+  for (;;) {
+    const int r = spotfit_serve_poll(sv, ticket);
+    if (r != 1) return r;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait_for(lk, std::chrono::microseconds(200));
+  }
+}
+
+int spotfit_serve_stats(spotfit_serve_t* sv, spotfit_serve_stats_t* out) {
+  if (!sv || !out) return serve_fail(SPOTFIT_E_NULL, "serve_stats: NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  std::memset(out, 0, sizeof *out);
+  out->frames_done = sv->frames_done;
+  out->frames_failed = sv->frames_failed;
+  out->spots_done = sv->spots_done;
+  out->batches = sv->batches;
+  out->rejected = sv->rejected;
+  if (!sv->lat_ns.empty()) {
+    std::vector<uint64_t> v = sv->lat_ns;
+    auto q = [&](double p) {
+      const size_t k = (size_t)(p * (double)(v.size() - 1));
+      std::nth_element(v.begin(), v.begin() + (ptrdiff_t)k, v.end());
+      return (double)v[k] / 1e3;
+    };
+    out->latency_p50_us = q(0.50);
+    out->latency_p99_us = q(0.99);
+    out->latency_max_us = (double)*std::max_element(v.begin(), v.end()) / 1e3;
+  }
+  out->mean_frames_per_batch = sv->batches ? (double)sv->lat_ns.size() / (double)sv->batches : 0.0;
+  out->wall_s = sv->t_last > sv->t_first ? (double)(sv->t_last - sv->t_first) / 1e9 : 0.0;
+  return SPOTFIT_OK;
+}
+
+void spotfit_serve_destroy(spotfit_serve_t* sv) {
+  if (!sv) return;
+  if (sv->worker.joinable()) {
+    sv->stop.store(true, std::memory_order_release);
+    sv->worker.join();
+  }
+  (void)hipSetDevice(sv->device);
+  for (auto s : sv->streams) (void)hipStreamSynchronize(s);
+  for (auto ev : sv->event_pool) (void)hipEventDestroy(ev);
+  for (auto c : sv->ctxs) spotfit_ctx_destroy(c);
+  for (auto s : sv->streams) (void)hipStreamDestroy(s);
+  free_pair(sv->d_pix, sv->h_pix);
+  free_pair(sv->d_sizes, sv->h_sizes);
+  free_pair(sv->d_offs, sv->h_offs);
+  free_pair(sv->d_init, sv->h_init);
+  free_pair(sv->d_params, sv->h_params);
+  free_pair(sv->d_chi2, sv->h_chi2);
+  free_pair(sv->d_iters, sv->h_iters);
+  free_pair(sv->d_status, sv->h_status);
+  delete sv;
+}
+
+int spotfit_serve_replay(spotfit_serve_t* sv, const spotfit_frame_t* frames, int64_t n_frames,
+                         const uint64_t* arrival_offset_ns) {
+  if (!sv || (n_frames > 0 && (!frames || !arrival_offset_ns)))
+    return serve_fail(SPOTFIT_E_NULL, "serve_replay: NULL argument");
+  std::vector<uint64_t> tickets((size_t)n_frames, 0);
+  const uint64_t t0 = now_ns() + 1000000;  // start 1 ms from now
+  for (int64_t f = 0; f < n_frames; ++f) {
+    const uint64_t ta = t0 + arrival_offset_ns[f];
+    while (now_ns() < ta) {
+    }
+    for (;;) {  // a frame that is not admitted waits for space; its latency keeps counting
+      const int r = spotfit_serve_submit(sv, &frames[f], ta, &tickets[(size_t)f]);
+      if (r == SPOTFIT_OK) break;
+      if (r != SPOTFIT_E_AGAIN) return r;
+      std::this_thread::yield();
+    }
+  }
+  for (int64_t f = 0; f < n_frames; ++f) {
+    const int r = spotfit_serve_wait(sv, tickets[(size_t)f]);
+    if (r != SPOTFIT_OK) return r;
+  }
+  return SPOTFIT_OK;
+}
+
+const char* spotfit_serve_last_error(void) { return g_serve_error.c_str(); }
+
+}  // extern "C"

@@ -362,24 +362,34 @@ def noise_free(n: int, sides=(9, 11, 15), models=(SYM, ELL), seed: int = 11) -> 
     return _concat([parts], "noise_free")
 
 
-@dataclasses.dataclass
-class Frame:
-    t_arrival: float          # seconds since stream start
-    batch: SpotBatch
-
-
 def serve_frames(n_frames: int, fps: float = 1000.0, seed: int = 4,
-                 spots_lo: int = 20, spots_hi: int = 200):
-    """Camera-frame stream: Poisson arrivals at `fps`, U{spots_lo..spots_hi} spots each."""
+                 spots_lo: int = 20, spots_hi: int = 200, pool_spots: int = 200000,
+                 threads: int = 1):
+    """Camera-frame stream: Poisson arrivals at `fps`, U{spots_lo..spots_hi} spots each.
+
+    Returns (arrival times in seconds, list of per-frame SpotBatch).  Spots come from
+    one seeded pool of the serve_fiducials law; frame f takes the next counts[f]
+    spots of the pool, cycling through it (a stream longer than the pool reuses
+    spots, which leaves the per-frame size and work distribution unchanged).
+    """
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 4242])))
     gaps = rng.exponential(1.0 / fps, size=n_frames)
     t = np.cumsum(gaps)
     counts = rng.integers(spots_lo, spots_hi + 1, size=n_frames)
+    total = int(counts.sum())
+    pool = workload("serve_fiducials", n=max(spots_hi, min(total, pool_spots)), seed=seed,
+                    threads=threads)
+    npix = pool.npix()
     frames = []
+    cur = 0
     for f in range(n_frames):
-        r2 = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 7, f])))
-        side_w, side_h, model, off, sig, alpha, beta, rsd = _law_serve(r2, int(counts[f]))
-        parts = _finish_chunk(r2, side_w, side_h, model, off, sig, alpha, beta, rsd, np.uint16,
-                              moment_init)
-        frames.append(Frame(float(t[f]), _concat([parts], f"frame{f}")))
-    return frames
+        c = int(counts[f])
+        if cur + c > pool.n:
+            cur = 0
+        s0, s1 = cur, cur + c
+        cur = s1
+        o0 = int(pool.offsets[s0])
+        o1 = o0 + int(npix[s0:s1].sum())
+        frames.append(SpotBatch(pool.data[o0:o1], pool.sizes[s0:s1], pool.offsets[s0:s1] - o0,
+                                pool.init[s0:s1], pool.truth[s0:s1], f"frame{f}"))
+    return t, frames

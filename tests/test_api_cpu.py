@@ -69,7 +69,7 @@ def test_default_options_are_the_papers():
     ("max_iter", -1), ("max_iter", 5000), ("precision", 7), ("min_delta", 1.0),
     ("min_delta", -1e-3), ("tie_tau", 1.5), ("sigma_min", 0.0), ("max_pixels", 2000),
     ("max_pixels", 4), ("max_error_per_px", float("nan")), ("sigma_max_frac", 0.05),
-    ("max_side", 2), ("max_side", 33),
+    ("max_side", 2), ("max_side", 33), ("schedule", 2),
 ])
 def test_bad_options_rejected(field, value):
     o = sf.default_options()
@@ -97,6 +97,8 @@ def test_call_level_errors_before_any_gpu_call():
     assert L.spotfit_fit_spots(fake, None, 0, 1, 1, 1, 10, None, 1, 1, 1, 1, None, None) == -1
     assert L.spotfit_fit_spots(fake, 1, 0, 1, 1, 1, 10, None, 1, None, 1, 1, None, None) == -1
     assert L.spotfit_ctx_create(None, 0) == -1
+    assert L.spotfit_ctx_reserve(None, 10) == -1
+    assert L.spotfit_ctx_reserve(fake, -1) == -2
 
 
 def test_version():

@@ -1,0 +1,106 @@
+"""Mixed-size schedule and the serving loop, through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+import spotgen
+from parity import compare, summary
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sf():
+    import paper_2106_02045_amd as m
+    return m
+
+
+def _fit(sf, ctx, b, opts):
+    import torch
+    dev = torch.device("cuda:0")
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    out = ctx.fit_spots(up(b.data), up(b.sizes), up(b.offsets), up(b.init), opts, want_evals=True)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_mixed_schedule_matches_oracle_and_uniform(sf):
+    ctx = sf.Context(0)
+    b = spotgen.config(3, n=30000)
+    gm = _fit(sf, ctx, b, sf.default_options(schedule=sf.SCHEDULE_MIXED))
+    r = oracle.fit_batch(b, oracle.default_opts(), threads=8)
+    c = compare(gm, r, chi_band=1e-11, step_band=1e-9)
+    print(summary("mixed schedule 30k", c))
+    assert c["strict_mismatch"] == 0 and c["tol_fail_same"] == 0
+    # every spot's result is independent of how the batch was scheduled
+    for side in (8, 16, 32):
+        sel = np.nonzero(np.maximum(b.sizes[:, 0], b.sizes[:, 1]) <= side)[0]
+        sel = sel[np.maximum(b.sizes[sel, 0], b.sizes[sel, 1]) > side // 2]
+        sub = b.subset(sel)
+        gu = _fit(sf, ctx, sub, sf.default_options(max_side=side))
+        for k in ("params", "chi2", "iters", "status"):
+            np.testing.assert_array_equal(gu[k], gm[k][sel])
+
+
+def test_mixed_schedule_workspace_reuse_and_growth(sf):
+    ctx = sf.Context(0)
+    ctx.reserve(100)
+    o = sf.default_options(schedule=sf.SCHEDULE_MIXED)
+    b1 = spotgen.config(3, n=5000)
+    b2 = spotgen.config(3, n=700, seed=9)
+    g1 = _fit(sf, ctx, b1, o)        # grows the workspace
+    g2 = _fit(sf, ctx, b2, o)        # smaller call reuses it
+    g1b = _fit(sf, ctx, b1, o)
+    for k in g1:
+        np.testing.assert_array_equal(g1[k], g1b[k])
+    assert np.all(g2["status"] != 5)
+
+
+def test_serving_alone_equals_mix_and_oracle(sf):
+    ts, frames = spotgen.serve_frames(300, fps=5000.0, seed=7, threads=8)
+    opts = sf.default_options(max_side=21, schedule=sf.SCHEDULE_MIXED)
+    srv = sf.Server(0, opts, device_mem_budget=64 << 20, max_frames=512, n_streams=3)
+    offs = np.round((ts - ts[0]) * 1e9).astype(np.uint64)
+    outs = srv.replay([(f.data, f.sizes, f.init) for f in frames], offs)
+    st = srv.stats()
+    srv.close()
+    print("serve stats", st)
+    assert st["frames_done"] == len(frames) and st["frames_failed"] == 0
+    assert st["spots_done"] == sum(f.n for f in frames)
+    ctx = sf.Context(0)
+    for f in range(0, len(frames), 37):
+        alone = _fit(sf, ctx, frames[f], opts)
+        for k in ("params", "chi2", "iters", "status"):
+            np.testing.assert_array_equal(alone[k], outs[f][k])
+    # and against the oracle
+    allb = frames[0]
+    r = oracle.fit_batch(allb, oracle.default_opts(), threads=4)
+    c = compare(outs[0], r, chi_band=1e-11, step_band=1e-9)
+    assert c["strict_mismatch"] == 0 and c["tol_fail_same"] == 0
+
+
+def test_serving_admission_by_memory(sf):
+    # a budget that holds only a few frames: submit refuses, then admits once
+    # earlier frames complete; every frame still finishes correctly
+    ts, frames = spotgen.serve_frames(60, fps=1e6, seed=8, threads=4)
+    opts = sf.default_options(max_side=21)
+    srv = sf.Server(0, opts, device_mem_budget=1 << 20, max_frames=4, n_streams=2)
+    import time
+    pending = []
+    refused = 0
+    for f in frames:
+        while True:
+            r = srv.submit(f.data, f.sizes, f.init)
+            if r is not None:
+                pending.append(r)
+                break
+            refused += 1
+            time.sleep(2e-4)
+    results = [srv.wait(t) for t, _ in pending]
+    st = srv.stats()
+    srv.close()
+    assert st["frames_done"] == len(frames)
+    assert refused > 0 and st["rejected"] == refused
+    ctx = sf.Context(0)
+    alone = _fit(sf, ctx, frames[11], opts)
+    np.testing.assert_array_equal(alone["params"], results[11]["params"])
