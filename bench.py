@@ -33,6 +33,34 @@ C_GRAD = {0: 66, 1: 88}
 C_TRIAL = 16
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources and headers the fit kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2106_02045_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "spotfit.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, precision: str, schedule: str):
+    """HBM bytes per launch of the fit kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known size), or None when
+    no summary exists for this configuration or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}_{schedule}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,9 +70,16 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="spots (default: the workload's size)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32", "plain"])
     ap.add_argument("--tie-tau", type=float, default=0.0)
+    ap.add_argument("--schedule", default="uniform", choices=["uniform", "mixed", "per-size"],
+                    help="uniform: one lane-group width for the batch; mixed: one persistent "
+                         "launch with per-size-class widths; per-size: one launch per ROI side "
+                         "(spots grouped by side on the host before timing)")
     ap.add_argument("--cpu-sample", type=int, default=1000000,
                     help="spots of the same workload fitted by the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-copy-mb", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB once: the "
+                         "calibration dispatch for hardware traffic counters")
     ap.add_argument("--parity-sample", type=int, default=2000,
                     help="spots compared with the CPU oracle after the timed run (0: none)")
     return ap.parse_args()
@@ -78,9 +113,34 @@ def main():
             "plain": sf.PREC_FP32_PLAIN}[a.precision]
     max_side = int(max(batch.sizes[:, 0].max(), batch.sizes[:, 1].max()))
     opts = sf.default_options(precision=prec, max_pixels=max(9, max_px), max_side=max(3, max_side),
-                              tie_tau=a.tie_tau)
+                              tie_tau=a.tie_tau,
+                              schedule=sf.SCHEDULE_MIXED if a.schedule == "mixed" else sf.SCHEDULE_UNIFORM)
+    if a.schedule == "mixed":
+        ctx.reserve(n)
     out = ctx.fit_spots(data, sizes, offs, init, opts, want_evals=True)
     torch.cuda.synchronize()
+
+    # per-size launches: the spots of each ROI side as their own batch, in device
+    # memory before timing; one step launches them all
+    groups = []
+    if a.schedule == "per-size":
+        side_of = np.maximum(batch.sizes[:, 0], batch.sizes[:, 1])
+        for side in np.unique(side_of):
+            idx = np.nonzero(side_of == side)[0]
+            sub = batch.subset(idx)
+            o2 = sf.default_options(precision=prec, max_pixels=max(9, int(sub.npix().max())),
+                                    max_side=int(max(3, side)), tie_tau=a.tie_tau)
+            groups.append((idx, o2, up(sub.data), up(sub.sizes), up(sub.offsets), up(sub.init),
+                           ctx.fit_spots(up(sub.data), up(sub.sizes), up(sub.offsets),
+                                         up(sub.init), o2)))
+        torch.cuda.synchronize()
+
+    def step(stream):
+        if groups:
+            for idx, o2, d, sz, of, it, ou in groups:
+                ctx.fit_spots(d, sz, of, it, o2, out=ou, stream=stream)
+        else:
+            ctx.fit_spots(data, sizes, offs, init, opts, out=out, stream=stream)
 
     # algorithmic work from the evaluation counts (the fit is deterministic, so the
     # timed launches below do exactly this work)
@@ -100,7 +160,7 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
     for _ in range(a.warmup):
-        ctx.fit_spots(data, sizes, offs, init, opts, out=out, stream=stream)
+        step(stream)
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
@@ -108,7 +168,7 @@ def main():
     w0 = time.perf_counter()
     for i in range(a.steps):
         starts[i].record(stream)
-        ctx.fit_spots(data, sizes, offs, init, opts, out=out, stream=stream)
+        step(stream)
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -116,6 +176,13 @@ def main():
     k_avg_s = sum(kms) / len(kms) / 1e3
     ms_per_step = wall / a.steps * 1e3
     fits_per_s = n / (wall / a.steps)
+
+    if a.pmc_copy_mb > 0:
+        src = torch.ones(a.pmc_copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     achieved_tflops = flops / k_avg_s / 1e12
     hbm_gbps = alg_bytes / k_avg_s / 1e9
@@ -143,8 +210,11 @@ def main():
         idx = np.sort(rng.choice(n, size=min(a.parity_sample, n), replace=False))
         r = oracle.fit_batch(batch.subset(idx), oracle.default_opts(tie_tau=a.tie_tau),
                              threads=min(os.cpu_count() or 1, 16))
-        g = {"params": out["params"].cpu().numpy()[idx], "chi2": out["chi2"].cpu().numpy()[idx],
-             "iters": out["iters"].cpu().numpy()[idx], "status": out["status"].cpu().numpy()[idx]}
+        full = {k: out[k].cpu().numpy() for k in ("params", "chi2", "iters", "status")}
+        for gidx, o2, d, sz, of, it, ou in groups:  # per-size results back in spot order
+            for k in full:
+                full[k][gidx] = ou[k].cpu().numpy()
+        g = {k: v[idx] for k, v in full.items()}
         c = compare(g, r, chi_band=1e-11, step_band=1e-9)
         parity = {"sample": len(idx), "status_mismatch": c["status_mismatch"],
                   "iters_mismatch": c["iters_mismatch"], "tol_fail": c["tol_fail_any"],
@@ -167,10 +237,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "spots": n, "roi": f"{batch.sizes[0,0]}x{batch.sizes[0,1]}"
                    if len(np.unique(npix)) == 1 else "mixed", "pixel_dtype": "u16",
-                   "precision": a.precision, "tie_tau": a.tie_tau},
+                   "precision": a.precision, "tie_tau": a.tie_tau, "schedule": a.schedule,
+                   "launches_per_step": max(1, len(groups))},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_ALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_ALU_TFLOPS,
-                     "traffic": None},
+                     "traffic": measured_traffic(a.workload, a.precision, a.schedule)},
         "hbm": {"achieved_algorithmic_GBps": hbm_gbps, "peak_GBps": PEAK_HBM_GBPS,
                 "frac": hbm_gbps / PEAK_HBM_GBPS, "bytes_per_launch": alg_bytes},
         "kernel_ms_avg": k_avg_s * 1e3,
