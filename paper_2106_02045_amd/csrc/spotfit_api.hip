@@ -22,10 +22,10 @@ struct spotfit_ctx {
   // separable kernel: plan used for each size class (max side <= 8, <= 16, <= 32)
   // and resident 64-lane workgroups per CU of every plan
   int plan_for_class[3];
-  int occ_plan[8];
+  int occ_plan[16];
   // mixed-size batches: plan and residency of the persistent kernel, workspace
   int mixed_plan;
-  int occ_mixed[4];
+  int occ_mixed[8];
   int32_t* ws;      // counters[8] then 3 lists of ws_cap spot indices
   int64_t ws_cap;
 };
@@ -154,18 +154,19 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
     }
     c->occ_mixed[pl] = nb > 0 ? nb : 1;
   }
-  c->mixed_plan = 0;
+  // default mixed-size plan: the narrow kernel's (4x2, 4x4, 16x2 lanes x columns)
+  c->mixed_plan = sf::mixed_plan_count() - sf::narrow_mixed_plan_count();
   if (const char* env = std::getenv("SPOTFIT_MIXED_PLAN")) {
     const int v = std::atoi(env);
     if (v >= 0 && v < sf::mixed_plan_count()) c->mixed_plan = v;
   }
   c->ws = nullptr;
   c->ws_cap = 0;
-  // default plan per size class (measured on MI355X): <= 8 px side: 8 lanes x 1
-  // column; <= 16: 16 lanes x 1 column; <= 32: 32 lanes x 1 column
-  c->plan_for_class[0] = 0;
-  c->plan_for_class[1] = 2;
-  c->plan_for_class[2] = 4;
+  // default plan per size class (measured on MI355X), all narrow: <= 8 px side:
+  // 4 lanes x 2 columns; <= 16: 4 lanes x 4 columns; <= 32: 16 lanes x 2 columns
+  c->plan_for_class[0] = sf::wide_plan_count() + 0;
+  c->plan_for_class[1] = sf::wide_plan_count() + 1;
+  c->plan_for_class[2] = sf::wide_plan_count() + 3;
   if (const char* env = std::getenv("SPOTFIT_GROUP_PLAN")) {
     // tuning override "a,b,c": plan for each size class
     int a = -1, b = -1, d = -1;
@@ -183,7 +184,7 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
     const int v = std::atoi(env);
     if (v > 0 && v <= 64) {
       for (int i = 0; i < 5; ++i) c->occupancy[i][0] = c->occupancy[i][1] = v;
-      for (int i = 0; i < 8; ++i) c->occ_plan[i] = v;
+      for (int i = 0; i < 16; ++i) c->occ_plan[i] = v;
     }
   }
   *out = c;

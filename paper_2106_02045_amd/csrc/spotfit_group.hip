@@ -36,12 +36,13 @@
 
 #include "spotfit.h"
 #include "spotfit_internal.h"
+#include "spotfit_lm.h"
 #include "xlane.h"
 
 namespace sf {
 namespace grp {
 
-enum Mode : int { kNew = 0, kTrialFirst = 1, kTrialRetry = 2 };
+using namespace lm;
 
 __device__ __forceinline__ void lds_sync() {
   // orders this wavefront's LDS writes before its later LDS reads
@@ -91,76 +92,6 @@ __device__ __forceinline__ double group_sum1(double v) {
   double a[1] = {v};
   halve_from<6 - GroupLog<L>::m, 1>(a);
   return a[0];
-}
-
-__device__ __forceinline__ double clampn(double v, double lo, double hi) {
-  return v < lo ? lo : (v > hi ? hi : v);
-}
-
-__device__ __forceinline__ double pow10i(int k) {
-  double t = 1.0;
-  const int m = k < 0 ? -k : k;
-  for (int i = 0; i < m; ++i) t *= 10.0;
-  return k < 0 ? 1.0 / t : t;
-}
-
-// 1/x from the hardware reciprocal refined by two Newton steps (~1 ulp).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
-// Solve (A + lam diag A) d = bv for the 4x4 symmetric A (upper triangle in
-// A[10]: 00 01 02 03 11 12 13 22 23 33) by an LDL^T factorisation; NaN when a
-// pivot is not positive (the matrix is not positive definite).
-__device__ __forceinline__ void solve4(const double* A, const double* bv, double lam, double* d) {
-  const double m00 = A[0] + lam * A[0], m11 = A[4] + lam * A[4];
-  const double m22 = A[7] + lam * A[7], m33 = A[9] + lam * A[9];
-  const double d0 = m00;
-  bool ok = d0 > 0.0;
-  const double i0 = rcp_nr(d0);
-  const double l10 = A[1] * i0, l20 = A[2] * i0, l30 = A[3] * i0;
-  const double d1 = m11 - l10 * l10 * d0;
-  ok = ok && d1 > 0.0;
-  const double i1 = rcp_nr(d1);
-  const double l21 = (A[5] - l20 * l10 * d0) * i1;
-  const double l31 = (A[6] - l30 * l10 * d0) * i1;
-  const double d2 = m22 - l20 * l20 * d0 - l21 * l21 * d1;
-  ok = ok && d2 > 0.0;
-  const double i2 = rcp_nr(d2);
-  const double l32 = (A[8] - l30 * l20 * d0 - l31 * l21 * d1) * i2;
-  const double d3 = m33 - l30 * l30 * d0 - l31 * l31 * d1 - l32 * l32 * d2;
-  ok = ok && d3 > 0.0;
-  const double i3 = rcp_nr(d3);
-  const double z0 = bv[0];
-  const double z1 = bv[1] - l10 * z0;
-  const double z2 = bv[2] - l20 * z0 - l21 * z1;
-  const double z3 = bv[3] - l30 * z0 - l31 * z1 - l32 * z2;
-  const double x3 = z3 * i3;
-  const double x2 = z2 * i2 - l32 * x3;
-  const double x1 = z1 * i1 - l21 * x2 - l31 * x3;
-  const double x0 = z0 * i0 - l10 * x1 - l20 * x2 - l30 * x3;
-  ok = ok && __builtin_isfinite(x0) && __builtin_isfinite(x1) && __builtin_isfinite(x2) &&
-       __builtin_isfinite(x3);
-  const double nanv = __builtin_nan("");
-  d[0] = ok ? x0 : nanv;
-  d[1] = ok ? x1 : nanv;
-  d[2] = ok ? x2 : nanv;
-  d[3] = ok ? x3 : nanv;
-}
-
-// Parameter j of (x, y, sx, sy): order of its x-moment and y-moment.
-//   df_x = dx/sx^2 f, df_y = dy/sy^2 f, df_sx = dx^2/sx^3 f, df_sy = dy^2/sy^3 f
-__device__ __forceinline__ int ox_of(int j) { return j == 0 ? 1 : j == 2 ? 2 : 0; }
-__device__ __forceinline__ int oy_of(int j) { return j == 1 ? 1 : j == 3 ? 2 : 0; }
-
-// Index pairs of the upper-triangle entries t = 0..9.
-__device__ __forceinline__ int tri_i(int t) { return t < 4 ? 0 : t < 7 ? 1 : t < 9 ? 2 : 3; }
-__device__ __forceinline__ int tri_j(int t) {
-  return t < 4 ? t : t < 7 ? t - 3 : t < 9 ? t - 5 : 3;
 }
 
 // red[] after the derivative-pass reduction (16 group sums):
@@ -727,9 +658,12 @@ static const void* sym_lw() {
 
 }  // namespace grp
 
-int group_plan_count() { return 5; }
+int wide_plan_count() { return 5; }
+
+int group_plan_count() { return wide_plan_count() + narrow_plan_count(); }
 
 void group_plan_shape(int plan, int* lanes, int* cpl) {
+  if (plan >= wide_plan_count()) return narrow_plan_shape(plan - wide_plan_count(), lanes, cpl);
 #define SF_SHAPE(I, L, C, W) \
   if (plan == I) {           \
     *lanes = L;              \
@@ -743,6 +677,7 @@ void group_plan_shape(int plan, int* lanes, int* cpl) {
 }
 
 const void* group_kernel_symbol(int plan) {
+  if (plan >= wide_plan_count()) return narrow_kernel_symbol(plan - wide_plan_count());
 #define SF_SYM(I, L, C, W) \
   if (plan == I) return grp::sym_lw<L, C, W>();
   SF_GROUP_PLANS(SF_SYM)
@@ -751,6 +686,7 @@ const void* group_kernel_symbol(int plan) {
 }
 
 hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t st) {
+  if (plan >= wide_plan_count()) return launch_narrow_kernel(plan - wide_plan_count(), ka, grid, st);
 #define SF_LAUNCH(I, L, C, W) \
   if (plan == I) return grp::launch_lw<L, C, W>(ka, grid, st);
   SF_GROUP_PLANS(SF_LAUNCH)
@@ -764,9 +700,12 @@ hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t 
   X(1, 8, 1, 8, 2, 32, 1, 2)    \
   X(2, 8, 1, 16, 1, 16, 2, 2)
 
-int mixed_plan_count() { return 3; }
+int wide_mixed_plan_count() { return 3; }
+
+int mixed_plan_count() { return wide_mixed_plan_count() + narrow_mixed_plan_count(); }
 
 const void* mixed_kernel_symbol(int plan) {
+  if (plan >= wide_mixed_plan_count()) return narrow_mixed_kernel_symbol(plan - wide_mixed_plan_count());
 #define SF_MSYM(I, A, B, C, D, E, F, W) \
   if (plan == I) return reinterpret_cast<const void*>(&grp::fit_mixed_kernel<A, B, C, D, E, F, W>);
   SF_MIXED_PLANS(SF_MSYM)
@@ -789,6 +728,8 @@ hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, 
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
+  if (plan >= wide_mixed_plan_count())
+    return launch_narrow_mixed_fit(plan - wide_mixed_plan_count(), ka, ws, grid, st);
 #define SF_MLAUNCH(I, A, B, C, D, E, F, W)                                                   \
   if (plan == I) {                                                                           \
     hipLaunchKernelGGL((grp::fit_mixed_kernel<A, B, C, D, E, F, W>), dim3(grid), dim3(64), 0, \

@@ -63,10 +63,23 @@ const void* mixed_kernel_symbol(int plan);
 hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, hipStream_t st);
 
 // Plans of the separable kernel: plan p groups `lanes` lanes per spot with `cpl`
-// columns per lane and holds spots with w, h <= lanes * cpl.
+// columns per lane and holds spots with w, h <= lanes * cpl.  Plans below
+// wide_plan_count() keep a group's state in LDS and share its scalar work over
+// the lanes; the narrow plans after them keep it in registers on every lane.
 int group_plan_count();
 void group_plan_shape(int plan, int* lanes, int* cpl);
 const void* group_kernel_symbol(int plan);
 hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t st);
+int wide_plan_count();
+
+int narrow_plan_count();
+void narrow_plan_shape(int plan, int* lanes, int* cpl);
+const void* narrow_kernel_symbol(int plan);
+hipError_t launch_narrow_kernel(int plan, const KArgs& ka, int grid, hipStream_t st);
+int narrow_mixed_plan_count();
+const void* narrow_mixed_kernel_symbol(int plan);
+// the fit launch of a mixed batch whose spots the classify pass has bucketed
+hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid,
+                                   hipStream_t st);
 
 }  // namespace sf

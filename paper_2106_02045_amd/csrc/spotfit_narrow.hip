@@ -1,0 +1,658 @@
+// spotfit_narrow.hip -- gfx950 kernel of the batched implicit-amplitude
+// Levenberg-Marquardt Gaussian-spot fit, separable form, narrow lane groups.
+//
+// The arithmetic is that of the separable kernel (f(r, c) = ex(c) * ey(r) for
+// Eq. 10 and its axis-aligned elliptical form, every sum of Eqs. 5-9 as
+// one-dimensional moments or bilinear forms, all in double precision, chi^2
+// summed directly over the pixels as Eq. 2 writes it).  What differs is the
+// mapping: a spot is held by a small group of L = 2, 4 or 8 lanes.
+//
+//  * Lane l of a group owns the columns c = l + L*j (j < CPL) with all their
+//    rows: the CPL*HM pixel values stay in registers (as float, exact for
+//    16-bit data) for the whole fit.  It computes ex(c) for its columns and
+//    ey(r) for the rows r = l + L*j; every lane then gathers all HM row
+//    factors from its group by DPP (or ds_swizzle) broadcasts.
+//  * The per-spot state (point, best point, normal equations, decisions) is
+//    kept in registers, identical on the L lanes: each lane takes every
+//    scalar step itself, so no LDS and no barriers are needed.
+//  * Group totals are log2(L) DPP butterfly steps; the two partners add the
+//    same two numbers, so every lane of a group holds bitwise the same total
+//    and takes the same branch.
+//
+// One trial evaluation costs per lane 2*CPL exponentials, ~7 double
+// operations per pixel it owns (two passes: the column sums t(c) = sum_r g ey
+// and row sums s(r) = sum_c g ex that give **G** and the derivative bilinear
+// forms; then the residual sum of squares), and a handful of group totals.
+//
+// The Levenberg-Marquardt loop is the same flattened per-group state machine
+// as the wide kernel (Fit2DGaussian pseudo-code): every wave step evaluates
+// each active group's candidate, takes its decisions, then runs the
+// derivative pass and the damped solve only where needed; a group whose spot
+// stops writes its result and fetches its next spot at once.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spotfit.h"
+#include "spotfit_internal.h"
+#include "spotfit_lm.h"
+#include "xlane.h"
+
+namespace sf {
+namespace nrw {
+
+using namespace lm;
+
+// Total over the L lanes of a group (L consecutive lanes, L a power of two
+// <= 16): butterfly over lane bits 0 (quad_perm [1,0,3,2]), 1 (quad_perm
+// [2,3,0,1]), 2 (row_half_mirror) and 3 (row_mirror).
+template <int L>
+__device__ __forceinline__ double gsum(double v) {
+  if constexpr (L >= 2) v += dpp_mov<0xB1>(v);
+  if constexpr (L >= 4) v += dpp_mov<0x4E>(v);
+  if constexpr (L >= 8) v += dpp_mov<0x141>(v);
+  if constexpr (L >= 16) v += dpp_mov<0x140>(v);
+  return v;
+}
+
+// Value of in-group lane Q on every lane of the group.
+template <int L, int Q>
+__device__ __forceinline__ int gbcast_i(int v) {
+  if constexpr (L == 1) {
+    return v;
+  } else if constexpr (L == 2) {
+    return __builtin_amdgcn_mov_dpp(v, Q == 0 ? 0xA0 : 0xF5, 0xF, 0xF, true);
+  } else if constexpr (L == 4) {
+    return __builtin_amdgcn_mov_dpp(v, Q * 0x55, 0xF, 0xF, true);
+  } else {
+    // ds_swizzle bit-mask mode inside 32 lanes: lane' = (lane & and) | Q
+    constexpr int andm = L == 8 ? 0x18 : 0x10;
+    return __builtin_amdgcn_ds_swizzle(v, andm | (Q << 5));
+  }
+}
+
+template <int L, int Q>
+__device__ __forceinline__ double gbcast(double v) {
+  int2 u = *reinterpret_cast<int2*>(&v);
+  int2 r = make_int2(gbcast_i<L, Q>(u.x), gbcast_i<L, Q>(u.y));
+  return *reinterpret_cast<double*>(&r);
+}
+
+// all[Q + L*j] = own[j] of in-group lane Q, for every Q < L.
+template <int L, int Q, int CPL, int HM>
+__device__ __forceinline__ void gather_rows(const double (&own)[CPL], double (&all)[HM]) {
+  if constexpr (Q < L) {
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) all[Q + L * j] = gbcast<L, Q>(own[j]);
+    gather_rows<L, Q + 1>(own, all);
+  }
+}
+
+// Zeros that the loads of a column outside a spot read instead (one row offset
+// of a 32 x 32 spot at most, as float or as 16-bit values).
+__device__ const float kZeros[32 * 32] = {};
+
+// Spots s = base + group, then + stride, ... of a uniform batch.
+struct StridedSrc {
+  int64_t n, base, stride;
+  __device__ int64_t first(int gi, int) const {
+    const int64_t s = base + gi;
+    return s < n ? s : -1;
+  }
+  __device__ int64_t next(int64_t s, int) const {
+    s += stride;
+    return s < n ? s : -1;
+  }
+};
+
+// Spots of one size class, taken from its list through an atomic counter.
+template <int L>
+struct QueueSrc {
+  const int32_t* list;
+  int32_t* take;
+  int32_t count;
+  __device__ int64_t pull(int li) const {
+    int v = 0;
+    if (li == 0) v = atomicAdd(take, 1);
+    v = gbcast_i<L, 0>(v);
+    return v < count ? (int64_t)list[v] : -1;
+  }
+  __device__ int64_t first(int, int li) const { return pull(li); }
+  __device__ int64_t next(int64_t, int li) const { return pull(li); }
+};
+
+// Per-group state kept in LDS between the steps of an iteration.
+struct NState {
+  double A[10];   // normal matrix at best (upper triangle 00 01 02 03 11 12 13 22 23 33)
+  double bv[4];   // right-hand side J^T (g - h) at best
+  double best[4];  // point at the start of the iteration
+  double chi_best, a_best, b_best;
+  // sums of the evaluation at pc that the derivative pass reuses
+  double Sx, Sxx, Sy, Syy, FG, D, Bx, Bsx, By, Bsy;
+};
+
+// Fit every spot the source hands to this wavefront's groups.
+// L lanes per spot, CPL columns per lane: spots with w, h <= L * CPL.
+template <int L, int CPL, class Src>
+__device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NState* sts) {
+  constexpr int HM = L * CPL;
+  const int lane = __lane_id();
+  const int gi = lane / L;
+  const int li = lane % L;
+  const KOpts o = ka.opt;
+  const double tau = o.tie_tau;
+
+  int64_t s = src.first(gi, li);
+  int w = 0, h = 0, k = 0, it = 0, status = 0, mode = kNew, n_grad = 0, n_trial = 0;
+  bool sym = true, small = false;
+
+  float g[CPL][HM];          // pixels of the lane's columns (0 outside the spot)
+  double ex[CPL], eyl[CPL];  // column factors of its columns, row factors of its rows
+  double pc[4] = {0.0, 0.0, 0.0, 0.0};  // candidate point (accepted point after a decision)
+  double a = 0.0, b = 0.0, chi = 0.0;   // Eq. 6 amplitudes and Eq. 2 error at pc
+  double Gs = 0.0, Tme = 0.0;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) ex[j] = eyl[j] = 0.0;
+  // Iteration state and the sums of the last evaluation, in LDS.  Every lane of
+  // a group computes the same values and writes them itself, so each lane only
+  // ever reads back its own writes: no synchronisation is needed.
+  NState& S = sts[gi];
+
+  // Fetch the next spot of this group, writing BAD_INPUT for unusable ones.
+  auto fetch = [&]() {
+    while (s >= 0) {
+      const spotfit_shape_t sh = ka.sizes[s];
+      const float* in = ka.init + 4 * s;
+      const float i0 = in[0], i1 = in[1], i2 = in[2], i3 = in[3];
+      const int mdl = sh.model;
+      const bool ell = mdl == SPOTFIT_ELL;
+      const bool bad = sh.w < 3 || sh.h < 3 || sh.w > HM || sh.h > HM ||
+                       sh.w * sh.h > o.max_pixels || sh.w > o.max_side || sh.h > o.max_side ||
+                       (mdl != SPOTFIT_SYM && !ell) || !__builtin_isfinite(i0) ||
+                       !__builtin_isfinite(i1) || !__builtin_isfinite(i2) || !(i2 > 0.f) ||
+                       (ell && (!__builtin_isfinite(i3) || !(i3 > 0.f)));
+      if (!bad) {
+        w = sh.w;
+        h = sh.h;
+        sym = !ell;
+        pc[0] = i0;
+        pc[1] = i1;
+        pc[2] = i2;
+        pc[3] = ell ? (double)i3 : (double)i2;
+        const int64_t off = ka.offsets[s];
+        // Every slot of the lane's columns is loaded at once, with no predicated
+        // load: a column outside the spot reads a block of zeros, a row below it
+        // repeats the spot's last row (every pass skips rows >= h).
+        double cs = 0.0;
+        if (ka.dtype == SPOTFIT_U16) {
+          const uint16_t* zero = reinterpret_cast<const uint16_t*>(kZeros);
+          const uint16_t* cp[CPL];  // top of each of the lane's columns
+#pragma unroll
+          for (int j = 0; j < CPL; ++j)
+            cp[j] = li + L * j < w ? static_cast<const uint16_t*>(ka.data) + off + li + L * j : zero;
+          uint32_t csi = 0;  // sum of the spot's pixels in the lane's columns (exact)
+#pragma unroll
+          for (int r = 0; r < HM; ++r) {
+            const uint32_t ro = uint32_t(r < h ? r : h - 1) * uint32_t(w);
+            uint32_t rs = 0;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+              const uint32_t v = cp[j][ro];
+              g[j][r] = float(v);
+              rs += v;
+            }
+            csi += r < h ? rs : 0u;
+          }
+          cs = double(csi);
+        } else {
+          const float* zero = kZeros;
+          const float* cp[CPL];
+#pragma unroll
+          for (int j = 0; j < CPL; ++j)
+            cp[j] = li + L * j < w ? static_cast<const float*>(ka.data) + off + li + L * j : zero;
+          double csj[CPL];
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) csj[j] = 0.0;
+#pragma unroll
+          for (int r = 0; r < HM; ++r) {
+            const uint32_t ro = uint32_t(r < h ? r : h - 1) * uint32_t(w);
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+              g[j][r] = cp[j][ro];
+              csj[j] += r < h ? double(g[j][r]) : 0.0;
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) cs += csj[j];
+        }
+        Gs = gsum<L>(cs);
+        Tme = o.max_error_per_px * double(w * h);
+        k = o.lambda0_exp10;
+        it = 0;
+        status = SPOTFIT_MAX_ITER;
+        mode = kNew;
+        n_grad = n_trial = 0;
+        return;
+      }
+      if (li == 0) {
+        const float nanf = __builtin_nanf("");
+#pragma unroll
+        for (int q = 0; q < 6; ++q) ka.params_out[6 * s + q] = nanf;
+        ka.chi2_out[s] = nanf;
+        ka.iters_out[s] = 0;
+        ka.status_out[s] = SPOTFIT_BAD_INPUT;
+        if (ka.evals_out) {
+          ka.evals_out[2 * s] = 0;
+          ka.evals_out[2 * s + 1] = 0;
+        }
+      }
+      s = src.next(s, li);
+    }
+  };
+
+  fetch();
+
+  while (__builtin_amdgcn_ballot_w64(s >= 0) != 0) {
+    if (s >= 0) {
+      // ================= trial evaluation at pc (Eqs. 2, 5, 6, 10) =================
+      {
+        const double x = pc[0], y = pc[1];
+        const double hx = -0.5 * rcp_nr(pc[2] * pc[2]);
+        const double hy = -0.5 * rcp_nr(pc[3] * pc[3]);
+        double sxp = 0.0, sxxp = 0.0, syp = 0.0, syyp = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int c = li + L * j;
+          const double dxc = double(c) - x, dyr = double(c) - y;
+          ex[j] = c < w ? exp(dxc * dxc * hx) : 0.0;
+          eyl[j] = c < h ? exp(dyr * dyr * hy) : 0.0;
+          sxp += ex[j];
+          sxxp = __builtin_fma(ex[j], ex[j], sxxp);
+          syp += eyl[j];
+          syyp = __builtin_fma(eyl[j], eyl[j], syyp);
+        }
+        double ey[HM];
+        gather_rows<L, 0>(eyl, ey);
+        // column sums t(c) = sum_r g ey and row sums s(r) = sum_c g ex (lane's columns);
+        // **G** = sum_r ey s(r), and the row-weighted forms of the derivative pass
+        double t[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) t[j] = 0.0;
+        double gp = 0.0, byp = 0.0, bsyp = 0.0;
+#pragma unroll
+        for (int r = 0; r < HM; ++r) {
+          if (r < h) {
+            const double e = ey[r];
+            double sr = 0.0;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+              const double gd = double(g[j][r]);
+              t[j] = __builtin_fma(gd, e, t[j]);
+              sr = __builtin_fma(gd, ex[j], sr);
+            }
+            const double dyr = double(r) - y;
+            const double es = e * sr;
+            gp += es;
+            byp = __builtin_fma(dyr, es, byp);
+            bsyp = __builtin_fma(dyr * dyr, es, bsyp);
+          }
+        }
+        double bxp = 0.0, bsxp = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const double dx = double(li + L * j) - x;
+          const double et = ex[j] * t[j];
+          bxp = __builtin_fma(dx, et, bxp);
+          bsxp = __builtin_fma(dx * dx, et, bsxp);
+        }
+        const double Sx = gsum<L>(sxp), Sxx = gsum<L>(sxxp);
+        const double Sy = gsum<L>(syp), Syy = gsum<L>(syyp);
+        const double FG = gsum<L>(gp);
+        S.Bx = gsum<L>(bxp);
+        S.Bsx = gsum<L>(bsxp);
+        S.By = gsum<L>(byp);
+        S.Bsy = gsum<L>(bsyp);
+        const double F = Sx * Sy, FF = Sxx * Syy;
+        const double Nn = double(w * h);
+        const double D = Nn * FF - F * F;
+        S.Sx = Sx;
+        S.Sxx = Sxx;
+        S.Sy = Sy;
+        S.Syy = Syy;
+        S.FG = FG;
+        S.D = D;
+        const bool okD = D > 0.0 && __builtin_isfinite(D);
+        const double iD = rcp_nr(D);
+        a = (Nn * FG - F * Gs) * iD;
+        b = (Gs * FF - F * FG) * iD;
+        // residual sum of squares, r = alpha f + beta - g over the spot's pixels
+        double aex[CPL], bm[CPL], c2[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          aex[j] = a * ex[j];
+          bm[j] = li + L * j < w ? b : 0.0;
+          c2[j] = 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < HM; ++r) {
+          if (r < h) {
+            const double e = ey[r];
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+              // a fresh conversion: reusing the first pass's doubles would keep
+              // all CPL*HM of them live in registers
+              float gv = g[j][r];
+              asm("" : "+v"(gv));
+              const double res = __builtin_fma(aex[j], e, bm[j] - double(gv));
+              c2[j] = __builtin_fma(res, res, c2[j]);
+            }
+          }
+        }
+        double c2s = c2[0];
+#pragma unroll
+        for (int j = 1; j < CPL; ++j) c2s += c2[j];
+        chi = gsum<L>(c2s);
+        if (!okD || !__builtin_isfinite(chi) || !__builtin_isfinite(a) || !__builtin_isfinite(b))
+          chi = __builtin_nan("");
+      }
+      if (mode != kNew) ++n_trial;
+
+      // ================= decisions (Fit2DGaussian loop) =================
+      bool start = false, do_grad = false, do_solve = false, done = false, out_best = false;
+      if (mode == kNew) {
+        start = true;
+      } else {
+        const double Chi = chi, chib = S.chi_best;
+        if (mode == kTrialFirst && Chi < chib * (1.0 - tau)) --k;  // improved: less damping
+        const bool worse = chib * (1.0 + tau) < Chi;
+        if (!small && worse && k < o.lambda_max_exp10) {
+          ++k;  // more damping, retry from best
+          mode = kTrialRetry;
+          do_solve = true;
+        } else if (worse || __builtin_isnan(Chi)) {
+          status = SPOTFIT_NOT_CONVERGED;
+          out_best = true;
+          done = true;
+        } else if (Chi < Tme) {
+          status = SPOTFIT_MAX_ERROR;
+          done = true;
+        } else if (chib * (1.0 - o.min_delta) < Chi) {
+          status = SPOTFIT_MIN_DELTA;
+          done = true;
+        } else if (small) {
+          status = SPOTFIT_MIN_STEP;
+          done = true;
+        } else {
+          start = true;
+        }
+      }
+      if (start) {  // a new iteration at the accepted point pc
+        if (it >= o.max_iter) {
+          status = SPOTFIT_MAX_ITER;
+          done = true;
+        } else {
+          ++it;
+          ++n_grad;
+          if (__builtin_isnan(chi)) {
+            status = SPOTFIT_NOT_CONVERGED;
+            done = true;
+          } else if (chi < Tme) {
+            status = SPOTFIT_MAX_ERROR;
+            done = true;
+          } else {
+            S.chi_best = chi;
+            S.a_best = a;
+            S.b_best = b;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) S.best[q] = pc[q];
+            mode = kTrialFirst;
+            do_grad = true;
+            do_solve = true;
+          }
+        }
+      }
+
+      // ================= derivative pass at pc (Eqs. 7-9, 11) =================
+      if (do_grad) {
+        const double x = pc[0], y = pc[1];
+        // moments of the lane's columns and rows
+        double v[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) v[q] = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int c = li + L * j;
+          const double dx = double(c) - x, dy = double(c) - y;
+          const double ex2 = ex[j] * ex[j], ey2 = eyl[j] * eyl[j];
+          const double dx2 = dx * dx, dy2 = dy * dy;
+          v[0] = __builtin_fma(dx, ex[j], v[0]);
+          v[1] = __builtin_fma(dx2, ex[j], v[1]);
+          v[2] = __builtin_fma(dx, ex2, v[2]);
+          v[3] = __builtin_fma(dx2, ex2, v[3]);
+          v[4] = __builtin_fma(dx2 * dx, ex2, v[4]);
+          v[5] = __builtin_fma(dx2 * dx2, ex2, v[5]);
+          v[6] = __builtin_fma(dy, eyl[j], v[6]);
+          v[7] = __builtin_fma(dy2, eyl[j], v[7]);
+          v[8] = __builtin_fma(dy, ey2, v[8]);
+          v[9] = __builtin_fma(dy2, ey2, v[9]);
+          v[10] = __builtin_fma(dy2 * dy, ey2, v[10]);
+          v[11] = __builtin_fma(dy2 * dy2, ey2, v[11]);
+        }
+#pragma unroll
+        for (int q = 0; q < 12; ++q) v[q] = gsum<L>(v[q]);
+        // X[k] = sum dx^k ex (k < 3), Xq[k] = sum dx^k ex^2 (k < 5); same for rows
+        const double Sx = S.Sx, Sxx = S.Sxx, Sy = S.Sy, Syy = S.Syy, FG = S.FG;
+        const double X[3] = {Sx, v[0], v[1]};
+        const double Xq[5] = {Sxx, v[2], v[3], v[4], v[5]};
+        const double Y[3] = {Sy, v[6], v[7]};
+        const double Yq[5] = {Syy, v[8], v[9], v[10], v[11]};
+        const double Bj[4] = {S.Bx, S.By, S.Bsx, S.Bsy};  // sum g d_j f / w_j for x, y, sx, sy
+        const double isx = rcp_nr(pc[2]), isy = rcp_nr(pc[3]);
+        const double Nn = double(w * h), iD = rcp_nr(S.D);
+        const double F = Sx * Sy, FF = Sxx * Syy;
+        const double wt[4] = {isx * isx, isy * isy, isx * isx * isx, isy * isy * isy};
+        // Eq. 7 sums of parameter j and Eq. 8 amplitude derivatives
+        double dF[4], Sfd[4], dFG[4], da[4], db[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int ox = ox_of(j), oy = oy_of(j);
+          dF[j] = X[ox] * Y[oy] * wt[j];
+          Sfd[j] = Xq[ox] * Yq[oy] * wt[j];
+          dFG[j] = Bj[j] * wt[j];
+          const double dFF = 2.0 * Sfd[j];
+          const double gam = Nn * dFF - 2.0 * F * dF[j];
+          da[j] = (Nn * dFG[j] - Gs * dF[j] - a * gam) * iD;
+          db[j] = (Gs * dFF - FG * dF[j] - F * dFG[j] - b * gam) * iD;
+        }
+        // normal matrix and right-hand side, J_j = da_j f + a df_j + db_j (Eq. 9, second factor)
+        double M[10];
+#pragma unroll
+        for (int t = 0; t < 10; ++t) {
+          const int i = tri_i(t), j = tri_j(t);
+          const double Sdd = Xq[ox_of(i) + ox_of(j)] * Yq[oy_of(i) + oy_of(j)] * wt[i] * wt[j];
+          M[t] = da[i] * da[j] * FF + a * (da[i] * Sfd[j] + da[j] * Sfd[i]) +
+                 (da[i] * db[j] + db[i] * da[j]) * F + a * a * Sdd +
+                 a * (db[j] * dF[i] + db[i] * dF[j]) + Nn * db[i] * db[j];
+        }
+        const double sfr = a * FF + b * F - FG;  // sum f r  (0 up to rounding, Eq. 4)
+        const double sr = a * F + b * Nn - Gs;   // sum r
+        double rhs[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          rhs[j] = -(da[j] * sfr + a * (a * Sfd[j] + b * dF[j] - dFG[j]) + db[j] * sr);
+        if (sym) {  // sigma = sx = sy: contract along d/dsigma = d/dsx + d/dsy, pad with identity
+          S.A[0] = M[0];
+          S.A[1] = M[1];
+          S.A[2] = M[2] + M[3];
+          S.A[3] = 0.0;
+          S.A[4] = M[4];
+          S.A[5] = M[5] + M[6];
+          S.A[6] = 0.0;
+          S.A[7] = M[7] + 2.0 * M[8] + M[9];
+          S.A[8] = 0.0;
+          S.A[9] = 1.0;
+          S.bv[0] = rhs[0];
+          S.bv[1] = rhs[1];
+          S.bv[2] = rhs[2] + rhs[3];
+          S.bv[3] = 0.0;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 10; ++t) S.A[t] = M[t];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) S.bv[j] = rhs[j];
+        }
+      }
+
+      // ================= damped step (Eq. 14) and limit() =================
+      if (do_solve) {
+        double d[4];
+        solve4(S.A, S.bv, pow10i(k), d);
+        const double smax = o.sigma_max_frac * double(w > h ? w : h);
+        const double b0 = S.best[0], b1 = S.best[1], b2 = S.best[2], b3 = S.best[3];
+        const double p2 = clampn(b2 + d[2], o.sigma_min, smax);
+        pc[0] = clampn(b0 + d[0], -0.5, double(w) - 0.5);
+        pc[1] = clampn(b1 + d[1], -0.5, double(h) - 0.5);
+        pc[2] = p2;
+        pc[3] = sym ? p2 : clampn(b3 + d[3], o.sigma_min, smax);
+        small = fabs(d[0]) < o.min_step_rel * fabs(b0) && fabs(d[1]) < o.min_step_rel * fabs(b1) &&
+                fabs(d[2]) < o.min_step_rel * fabs(b2) &&
+                (sym || fabs(d[3]) < o.min_step_rel * fabs(b3));
+      }
+
+      // ================= results and the next spot =================
+      if (done) {
+        if (li == 0) {
+          float* po = ka.params_out + 6 * s;
+          if (out_best) {
+            po[0] = float(S.best[0]);
+            po[1] = float(S.best[1]);
+            po[2] = float(S.best[2]);
+            po[3] = float(S.best[3]);
+            po[4] = float(S.a_best);
+            po[5] = float(S.b_best);
+            ka.chi2_out[s] = float(S.chi_best);
+          } else {
+            po[0] = float(pc[0]);
+            po[1] = float(pc[1]);
+            po[2] = float(pc[2]);
+            po[3] = float(pc[3]);
+            po[4] = float(a);
+            po[5] = float(b);
+            ka.chi2_out[s] = float(chi);
+          }
+          ka.iters_out[s] = it;
+          ka.status_out[s] = status;
+          if (ka.evals_out) {
+            ka.evals_out[2 * s] = n_grad;
+            ka.evals_out[2 * s + 1] = n_trial;
+          }
+        }
+        s = src.next(s, li);
+        fetch();
+      }
+    }
+  }
+}
+
+template <int L, int CPL, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_narrow_kernel(KArgs ka) {
+  constexpr int G = 64 / L;
+  __shared__ NState sts[G];
+  const StridedSrc src{ka.n, (int64_t)blockIdx.x * G, (int64_t)gridDim.x * G};
+  fit_narrow<L, CPL>(ka, src, sts);
+}
+
+// Batches of uneven spot sizes: the classify pass of the wide kernel's mixed
+// launch buckets spots by size class; each wavefront runs the plan of one class
+// and moves on to the next class when that class's list runs dry.
+template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_narrow_mixed_kernel(
+    KArgs ka, MixedWs ws) {
+  __shared__ NState sts[64 / L0];
+  static_assert(L0 <= L1 && L1 <= L2, "classes in order of size");
+  const int start = blockIdx.x % 3;
+  for (int q = 0; q < 3; ++q) {
+    const int c = (start + q) % 3;
+    const int32_t* list = ws.lists + (int64_t)c * ws.cap;
+    int32_t* take = ws.counters + 3 + c;
+    const int32_t count = ws.counters[c];
+    if (c == 0)
+      fit_narrow<L0, C0>(ka, QueueSrc<L0>{list, take, count}, sts);
+    else if (c == 1)
+      fit_narrow<L1, C1>(ka, QueueSrc<L1>{list, take, count}, sts);
+    else
+      fit_narrow<L2, C2>(ka, QueueSrc<L2>{list, take, count}, sts);
+  }
+}
+
+}  // namespace nrw
+
+// The compiled narrow plans: (lanes per spot, columns per lane, min waves per SIMD).
+#define SF_NARROW_PLANS(X) \
+  X(0, 4, 2, 3)            \
+  X(1, 4, 4, 2)            \
+  X(2, 8, 2, 2)            \
+  X(3, 16, 2, 2)
+
+int narrow_plan_count() { return 4; }
+
+void narrow_plan_shape(int plan, int* lanes, int* cpl) {
+#define SF_NSHAPE(I, L, C, W) \
+  if (plan == I) {            \
+    *lanes = L;               \
+    *cpl = C;                 \
+    return;                   \
+  }
+  SF_NARROW_PLANS(SF_NSHAPE)
+#undef SF_NSHAPE
+  *lanes = 0;
+  *cpl = 0;
+}
+
+const void* narrow_kernel_symbol(int plan) {
+#define SF_NSYM(I, L, C, W) \
+  if (plan == I) return reinterpret_cast<const void*>(&nrw::fit_narrow_kernel<L, C, W>);
+  SF_NARROW_PLANS(SF_NSYM)
+#undef SF_NSYM
+  return nullptr;
+}
+
+// Mixed-size plans (size classes <= 8, <= 16, <= 32 px side): lanes and columns
+// per class, min waves per SIMD.
+#define SF_NARROW_MIXED_PLANS(X) X(0, 4, 2, 4, 4, 16, 2, 2)
+
+int narrow_mixed_plan_count() { return 1; }
+
+const void* narrow_mixed_kernel_symbol(int plan) {
+#define SF_NMSYM(I, A, B, C, D, E, F, W) \
+  if (plan == I)                         \
+    return reinterpret_cast<const void*>(&nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W>);
+  SF_NARROW_MIXED_PLANS(SF_NMSYM)
+#undef SF_NMSYM
+  return nullptr;
+}
+
+hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid,
+                                   hipStream_t st) {
+#define SF_NMLAUNCH(I, A, B, C, D, E, F, W)                                                    \
+  if (plan == I) {                                                                             \
+    hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W>), dim3(grid), dim3(64), \
+                       0, st, ka, ws);                                                         \
+    return hipGetLastError();                                                                  \
+  }
+  SF_NARROW_MIXED_PLANS(SF_NMLAUNCH)
+#undef SF_NMLAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_narrow_kernel(int plan, const KArgs& ka, int grid, hipStream_t st) {
+#define SF_NLAUNCH(I, L, C, W)                                                               \
+  if (plan == I) {                                                                           \
+    hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W>), dim3(grid), dim3(64), 0, st, ka); \
+    return hipGetLastError();                                                                \
+  }
+  SF_NARROW_PLANS(SF_NLAUNCH)
+#undef SF_NLAUNCH
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sf

@@ -20,17 +20,19 @@ namespace sf {
 __device__ __forceinline__ unsigned as_u(float v) { return __float_as_uint(v); }
 __device__ __forceinline__ float as_f(unsigned v) { return __uint_as_float(v); }
 
+// DPP moves with bound_ctrl set: the patterns used here never read an invalid
+// lane, and no "old" value has to be materialised first.
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
   int2 u = *reinterpret_cast<int2*>(&v);
   int2 r;
-  r.x = __builtin_amdgcn_update_dpp(0, u.x, CTRL, 0xF, 0xF, false);
-  r.y = __builtin_amdgcn_update_dpp(0, u.y, CTRL, 0xF, 0xF, false);
+  r.x = __builtin_amdgcn_mov_dpp(u.x, CTRL, 0xF, 0xF, true);
+  r.y = __builtin_amdgcn_mov_dpp(u.y, CTRL, 0xF, 0xF, true);
   return *reinterpret_cast<double*>(&r);
 }
 
