@@ -166,6 +166,71 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                       float* chi2_out, int32_t* iters_out, int32_t* status_out,
                       int32_t* evals_out, void* stream);
 
+/* Start values on the device, so that raw spots go in and fits come out
+ * without a host round trip (the paper takes start values as given and leaves
+ * them out of its timings, Results section).  The estimate: background b0 =
+ * median of the border ring (top and bottom rows, left and right columns
+ * without the corners; the mean of the two middle values), weights
+ * max(g - b0, 0), centre = weighted centroid, var_x = sum w (x - cx)^2 / sum w
+ * (var_y alike); symmetric sigma = sqrt((var_x + var_y) / 2), elliptical
+ * sigma_x = sqrt(var_x), sigma_y = sqrt(var_y); sigmas clamped to
+ * [0.8, max(w, h) / 4]; a spot with no pixel above b0 starts at the ROI centre
+ * with sigma 1.5.  Writes init_out float[n][4] (device, caller-owned) on
+ * `stream`, ready for spotfit_fit_spots; spots that a fit with these options
+ * would reject (shape beyond opt->max_side / max_pixels, w or h < 3, unknown
+ * model) get NaN.  opt NULL = defaults.  Allocates nothing.  Returns
+ * SPOTFIT_OK or a negative spotfit_error_t (checked on the host first). */
+int spotfit_moment_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                        const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n_spots,
+                        const spotfit_options_t* opt, float* init_out, void* stream);
+
+/* Stop reasons and iteration counts of a fitted batch: the statistics the
+ * paper reports in its Number of iterations section (Fig. 8). */
+typedef struct {
+  int64_t n_spots;
+  int64_t status_count[6];  /* spots per spotfit_status_t                         */
+  int64_t iters_hist[65];   /* spots per iteration count 0..63; [64]: 64 or more  */
+  int64_t grad_evals;       /* totals over evals_out (0 when it is NULL)          */
+  int64_t trial_evals;
+} spotfit_stats_t;
+
+/* Summarise the device arrays status[n], iters[n] and evals[n][2] (evals may be
+ * NULL) of a fit enqueued earlier on `stream`: a histogram kernel runs on the
+ * stream, then the call waits for the stream and fills *out (host).  Uses a
+ * buffer the context owns.  Returns SPOTFIT_OK, SPOTFIT_E_NULL, SPOTFIT_E_ARG
+ * (n < 0) or SPOTFIT_E_HIP. */
+int spotfit_get_stats(spotfit_ctx_t* ctx, const int32_t* status, const int32_t* iters,
+                      const int32_t* evals, int64_t n_spots, spotfit_stats_t* out, void* stream);
+
+/* Which lane mapping the autotuner timed and which it kept. */
+typedef struct {
+  int32_t schedule;      /* spotfit_schedule_t that was tuned                       */
+  int32_t size_class;    /* uniform: 0 (max_side <= 8), 1 (<= 16), 2 (<= 32); mixed: -1 */
+  int32_t n_candidates;  /* entries used in plan_id / plan_ms                        */
+  int32_t chosen;        /* index of the kept plan in plan_id                        */
+  int32_t plan_id[16];   /* internal plan numbers (the SPOTFIT_GROUP_PLAN /
+                            SPOTFIT_MIXED_PLAN override values)                      */
+  double plan_ms[16];    /* mean time of one fit call with that plan                 */
+} spotfit_tune_report_t;
+
+/* Autotune the separable double-precision kernel on a representative batch
+ * (arguments as for spotfit_fit_spots; opt->precision must be
+ * SPOTFIT_PREC_FP64).  Every compiled lane mapping that can hold the batch is
+ * timed: for the uniform schedule, the plans whose group holds spots of
+ * opt->max_side; for the mixed schedule, the mixed-size plans.  Each plan gets
+ * one warm-up call and `reps` (>= 1) timed calls on `stream`, which the call
+ * waits for; the fastest is kept in the context for later calls with that
+ * schedule and size class.  The output arrays hold the last call's results.
+ * All plans take the same decisions on every spot, but their sums run in
+ * different orders, so results can differ in the last bits between plans: a
+ * context is bitwise reproducible between tunings.  report may be NULL.
+ * Returns SPOTFIT_OK or a negative spotfit_error_t. */
+int spotfit_autotune(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                     const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
+                     int64_t n_spots, const spotfit_options_t* opt, float* params_out,
+                     float* chi2_out, int32_t* iters_out, int32_t* status_out, int32_t reps,
+                     spotfit_tune_report_t* report, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving loop for camera frames (real-time tracking of fiducial spots).    */
 /* ------------------------------------------------------------------------ */

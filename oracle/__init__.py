@@ -89,6 +89,10 @@ def lib():
                                     ctypes.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.c_int]
         L.orc_fit_batch.restype = ctypes.c_int
+        L.orc_moment_init.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_moment_init.restype = ctypes.c_int
+        L.orc_moment_init_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp]
+        L.orc_moment_init_batch.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -176,4 +180,26 @@ def fit_batch(batch, opts: Optional[Opts] = None, threads: int = 1) -> dict:
                                                             "margin_step")), int(threads))
     if rc != 0:
         raise RuntimeError(f"orc_fit_batch failed ({rc})")
+    return out
+
+
+def moment_init(g, w: int, h: int, model: int) -> np.ndarray:
+    """Centroid / second-moment start values of one spot (orc_moment_init)."""
+    g = np.ascontiguousarray(g, dtype=np.float64).ravel()
+    out = np.empty(4)
+    lib().orc_moment_init(_dp(g), int(w), int(h), int(model), _dp(out))
+    return out
+
+
+def moment_init_batch(batch) -> np.ndarray:
+    """orc_moment_init over a SpotBatch; float64 [n, 4]."""
+    data = np.ascontiguousarray(batch.data)
+    dtype = 0 if data.dtype == np.uint16 else 1
+    if dtype == 1 and data.dtype != np.float32:
+        raise TypeError("data must be uint16 or float32")
+    sizes = np.ascontiguousarray(batch.sizes, dtype=np.uint8)
+    offs = np.ascontiguousarray(batch.offsets, dtype=np.int64)
+    out = np.empty((batch.n, 4))
+    lib().orc_moment_init_batch(data.ctypes.data, dtype, sizes.ctypes.data, offs.ctypes.data,
+                                int(batch.n), out.ctypes.data)
     return out

@@ -401,3 +401,86 @@ int orc_fit_batch(const void* data, int dtype, const uint8_t* sizes, const int64
   free(th);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Start values from the pixels (not part of the paper's method, which takes */
+/* start values as given, Results section): the centroid / second-moment     */
+/* estimate.  Background b0 = median of the border ring (top row, bottom row, */
+/* then the left and right columns without the corners; an even count, so   */
+/* the mean of the two middle values); weights wt = max(g - b0, 0); centre = */
+/* the weighted centroid; symmetric sigma^2 = (var_x + var_y) / 2, elliptical */
+/* sigma_x^2 = var_x, sigma_y^2 = var_y, with var_x = sum wt (x - cx)^2 /     */
+/* sum wt; sigmas clamped to [0.8, max(w, h) / 4]; with no positive weight   */
+/* the ROI centre and sigma 1.5.                                             */
+/* ------------------------------------------------------------------------ */
+int orc_moment_init(const double* g, int w, int h, int model, double* out) {
+  for (int i = 0; i < 4; ++i) out[i] = NAN;
+  if (w < 3 || h < 3 || w * h > ORC_MAXPIX || orc_nparams(model) == 0) return -1;
+  double ring[4 * 32];
+  int n = 0;
+  for (int c = 0; c < w; ++c) ring[n++] = g[c];
+  for (int c = 0; c < w; ++c) ring[n++] = g[(h - 1) * w + c];
+  for (int r = 1; r < h - 1; ++r) ring[n++] = g[r * w];
+  for (int r = 1; r < h - 1; ++r) ring[n++] = g[r * w + w - 1];
+  for (int i = 1; i < n; ++i) { /* insertion sort */
+    const double v = ring[i];
+    int j = i - 1;
+    while (j >= 0 && ring[j] > v) { ring[j + 1] = ring[j]; --j; }
+    ring[j + 1] = v;
+  }
+  const double b0 = 0.5 * (ring[n / 2 - 1] + ring[n / 2]);
+  double sw = 0.0, swx = 0.0, swy = 0.0;
+  for (int r = 0; r < h; ++r)
+    for (int c = 0; c < w; ++c) {
+      const double wt = fmax(g[r * w + c] - b0, 0.0);
+      sw += wt;
+      swx += wt * c;
+      swy += wt * r;
+    }
+  if (!(sw > 0.0)) {
+    out[0] = 0.5 * (w - 1);
+    out[1] = 0.5 * (h - 1);
+    out[2] = out[3] = 1.5;
+    return 0;
+  }
+  const double cx = swx / sw, cy = swy / sw;
+  double vx = 0.0, vy = 0.0;
+  for (int r = 0; r < h; ++r)
+    for (int c = 0; c < w; ++c) {
+      const double wt = fmax(g[r * w + c] - b0, 0.0);
+      vx += wt * (c - cx) * (c - cx);
+      vy += wt * (r - cy) * (r - cy);
+    }
+  vx /= sw;
+  vy /= sw;
+  double sx, sy;
+  if (model == ORC_SYM) {
+    sx = sy = sqrt(0.5 * (vx + vy));
+  } else {
+    sx = sqrt(vx);
+    sy = sqrt(vy);
+  }
+  const double lo = 0.8, hi = 0.25 * (w > h ? w : h);
+  out[0] = cx;
+  out[1] = cy;
+  out[2] = sx < lo ? lo : (sx > hi ? hi : sx);
+  out[3] = sy < lo ? lo : (sy > hi ? hi : sy);
+  return 0;
+}
+
+int orc_moment_init_batch(const void* data, int dtype, const uint8_t* sizes,
+                          const int64_t* offsets, int64_t n, double* out) {
+  double g[ORC_MAXPIX];
+  for (int64_t s = 0; s < n; ++s) {
+    const int w = sizes[4 * s], h = sizes[4 * s + 1], model = sizes[4 * s + 2];
+    if (w < 3 || h < 3 || w * h > ORC_MAXPIX) {
+      for (int i = 0; i < 4; ++i) out[4 * s + i] = NAN;
+      continue;
+    }
+    for (int k = 0; k < w * h; ++k)
+      g[k] = dtype == 0 ? (double)((const uint16_t*)data)[offsets[s] + k]
+                        : (double)((const float*)data)[offsets[s] + k];
+    orc_moment_init(g, w, h, model, out + 4 * s);
+  }
+  return 0;
+}

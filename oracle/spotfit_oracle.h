@@ -17,6 +17,10 @@
  *              search on tiny spots, and statistically by Table 1 / Fig. 8.
  *   The status codes, the MaxError threshold "A/3", the limit() box and the
  *   chi^2 normalisation are the paper's unspecified details: parity unpinned.
+ *   orc_moment_init  (start values, outside the paper's method) pinned by
+ *              hand-built images with known centroid / moments, the flat and
+ *              single-pixel degenerate cases, and an independent vectorised
+ *              implementation of the same estimate.
  */
 #ifndef SPOTFIT_ORACLE_H
 #define SPOTFIT_ORACLE_H
@@ -85,6 +89,17 @@ int orc_fit_batch(const void* data, int dtype, const uint8_t* sizes, const int64
                   const float* init, int64_t n, const orc_opts* o, double* params,
                   double* chi2, int32_t* iters, int32_t* status, int32_t* n_grad,
                   int32_t* n_trial, double* margin_chi, double* margin_step, int n_threads);
+
+/* Centroid / second-moment start values of one spot (row-major g, w x h):
+ * background = median of the border ring, weights max(g - b0, 0), weighted
+ * centroid and variances, sigmas clamped to [0.8, max(w, h) / 4]; no positive
+ * weight: ROI centre, sigma 1.5.  out = (x, y, sigma_x, sigma_y); returns 0,
+ * or -1 (NaN out) for w or h < 3, more than 1024 pixels or an unknown model. */
+int orc_moment_init(const double* g, int w, int h, int model, double* out);
+
+/* The same for a ragged batch in the library's layout; out double[n][4]. */
+int orc_moment_init_batch(const void* data, int dtype, const uint8_t* sizes,
+                          const int64_t* offsets, int64_t n, double* out);
 
 #ifdef __cplusplus
 }

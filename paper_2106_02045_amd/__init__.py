@@ -26,7 +26,8 @@ EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_
             "spotfit_last_error", "spotfit_version", "spotfit_serve_create",
             "spotfit_serve_submit", "spotfit_serve_poll", "spotfit_serve_wait",
             "spotfit_serve_stats", "spotfit_serve_destroy", "spotfit_serve_replay",
-            "spotfit_serve_last_error"]
+            "spotfit_serve_last_error", "spotfit_get_stats", "spotfit_autotune",
+            "spotfit_moment_init"]
 E_AGAIN = -6
 
 
@@ -85,6 +86,29 @@ class ServeStats(ctypes.Structure):
     ]
 
 
+class Stats(ctypes.Structure):
+    """Mirror of spotfit_stats_t."""
+    _fields_ = [
+        ("n_spots", ctypes.c_int64),
+        ("status_count", ctypes.c_int64 * 6),
+        ("iters_hist", ctypes.c_int64 * 65),
+        ("grad_evals", ctypes.c_int64),
+        ("trial_evals", ctypes.c_int64),
+    ]
+
+
+class TuneReport(ctypes.Structure):
+    """Mirror of spotfit_tune_report_t."""
+    _fields_ = [
+        ("schedule", ctypes.c_int32),
+        ("size_class", ctypes.c_int32),
+        ("n_candidates", ctypes.c_int32),
+        ("chosen", ctypes.c_int32),
+        ("plan_id", ctypes.c_int32 * 16),
+        ("plan_ms", ctypes.c_double * 16),
+    ]
+
+
 _lib = None
 
 
@@ -132,6 +156,14 @@ def lib():
         L.spotfit_serve_replay.restype = ctypes.c_int
         L.spotfit_serve_last_error.argtypes = []
         L.spotfit_serve_last_error.restype = ctypes.c_char_p
+        L.spotfit_moment_init.argtypes = [vp, vp, i32, vp, vp, i64, ctypes.POINTER(Options), vp,
+                                          vp]
+        L.spotfit_moment_init.restype = ctypes.c_int
+        L.spotfit_get_stats.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(Stats), vp]
+        L.spotfit_get_stats.restype = ctypes.c_int
+        L.spotfit_autotune.argtypes = [vp, vp, i32, vp, vp, vp, i64, ctypes.POINTER(Options),
+                                       vp, vp, vp, vp, i32, ctypes.POINTER(TuneReport), vp]
+        L.spotfit_autotune.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -191,15 +223,8 @@ class Context:
                                        params_ptr, chi2_ptr, iters_ptr, status_ptr,
                                        evals_ptr or None, stream_ptr or None)
 
-    def fit_spots(self, data, sizes, offsets, init, opts: Optional[Options] = None,
-                  out=None, want_evals: bool = False, stream=None):
-        """Fit spots held in torch CUDA tensors; returns a dict of output tensors.
-
-        data: uint16 or float32 [total pixels]; sizes: uint8 [n, 4]; offsets: int64 [n];
-        init: float32 [n, 4].  Outputs are allocated with torch unless `out` supplies
-        them (dict with params, chi2, iters, status[, evals]).  Enqueued on `stream`
-        (default: torch's current stream); synchronise before reading the outputs.
-        """
+    @staticmethod
+    def _marshal(data, sizes, offsets, init, out, want_evals):
         import torch
         n = int(sizes.shape[0])
         dev = data.device
@@ -224,7 +249,20 @@ class Context:
                        status=torch.empty(n, dtype=torch.int32, device=dev))
             if want_evals:
                 out["evals"] = torch.empty((n, 2), dtype=torch.int32, device=dev)
-        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        return n, dt, out
+
+    def fit_spots(self, data, sizes, offsets, init, opts: Optional[Options] = None,
+                  out=None, want_evals: bool = False, stream=None):
+        """Fit spots held in torch CUDA tensors; returns a dict of output tensors.
+
+        data: uint16 or float32 [total pixels]; sizes: uint8 [n, 4]; offsets: int64 [n];
+        init: float32 [n, 4].  Outputs are allocated with torch unless `out` supplies
+        them (dict with params, chi2, iters, status[, evals]).  Enqueued on `stream`
+        (default: torch's current stream); synchronise before reading the outputs.
+        """
+        import torch
+        n, dt, out = self._marshal(data, sizes, offsets, init, out, want_evals)
+        st = stream if stream is not None else torch.cuda.current_stream(data.device)
         rc = self.fit_spots_raw(data.data_ptr(), dt, sizes.data_ptr(), offsets.data_ptr(),
                                 init.data_ptr(), n, opts, out["params"].data_ptr(),
                                 out["chi2"].data_ptr(), out["iters"].data_ptr(),
@@ -233,6 +271,63 @@ class Context:
                                 st.cuda_stream)
         _check(rc, "spotfit_fit_spots")
         return out
+
+    def autotune(self, data, sizes, offsets, init, opts: Optional[Options] = None, reps: int = 3,
+                 out=None, stream=None):
+        """Time every lane mapping on this batch and keep the fastest (spotfit_autotune).
+
+        Returns (outputs of the kept plan, report dict with plan ids, ms per call, chosen)."""
+        import torch
+        n, dt, out = self._marshal(data, sizes, offsets, init, out, False)
+        st = stream if stream is not None else torch.cuda.current_stream(data.device)
+        rep = TuneReport()
+        rc = lib().spotfit_autotune(self._h, data.data_ptr(), dt, sizes.data_ptr(),
+                                    offsets.data_ptr(), init.data_ptr(), n,
+                                    ctypes.byref(opts) if opts is not None else None,
+                                    out["params"].data_ptr(), out["chi2"].data_ptr(),
+                                    out["iters"].data_ptr(), out["status"].data_ptr(), int(reps),
+                                    ctypes.byref(rep), st.cuda_stream)
+        _check(rc, "spotfit_autotune")
+        k = rep.n_candidates
+        report = dict(schedule=rep.schedule, size_class=rep.size_class,
+                      plan_id=list(rep.plan_id[:k]), plan_ms=list(rep.plan_ms[:k]),
+                      chosen_plan=rep.plan_id[rep.chosen])
+        return out, report
+
+    def moment_init(self, data, sizes, offsets, opts: Optional[Options] = None, out=None,
+                    stream=None):
+        """Start values on the device (spotfit_moment_init); returns float32 [n, 4]."""
+        import torch
+        n = int(sizes.shape[0])
+        dt = U16 if data.dtype == torch.uint16 else F32 if data.dtype == torch.float32 else None
+        if dt is None:
+            raise TypeError(f"data must be uint16 or float32, got {data.dtype}")
+        for name, t, want in (("sizes", sizes, torch.uint8), ("offsets", offsets, torch.int64)):
+            if t.dtype != want or not t.is_contiguous() or t.device != data.device:
+                raise TypeError(f"{name} must be a contiguous {want} tensor on {data.device}")
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device=data.device)
+        st = stream if stream is not None else torch.cuda.current_stream(data.device)
+        rc = lib().spotfit_moment_init(self._h, data.data_ptr(), dt, sizes.data_ptr(),
+                                       offsets.data_ptr(), n,
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       out.data_ptr(), st.cuda_stream)
+        _check(rc, "spotfit_moment_init")
+        return out
+
+    def stats(self, out, stream=None):
+        """Stop reasons, iteration histogram and evaluation totals of a fit's outputs."""
+        import torch
+        n = int(out["status"].shape[0])
+        st = stream if stream is not None else torch.cuda.current_stream(out["status"].device)
+        res = Stats()
+        rc = lib().spotfit_get_stats(self._h, out["status"].data_ptr(), out["iters"].data_ptr(),
+                                     out["evals"].data_ptr() if "evals" in out else None, n,
+                                     ctypes.byref(res), st.cuda_stream)
+        _check(rc, "spotfit_get_stats")
+        return dict(n_spots=res.n_spots, status_count=list(res.status_count),
+                    iters_hist=list(res.iters_hist), grad_evals=res.grad_evals,
+                    trial_evals=res.trial_evals)
 
 
 def version() -> int:

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["spotfit_kernels.hip", "spotfit_group.hip", "spotfit_narrow.hip", "spotfit_plain.hip", "spotfit_api.hip",
+SOURCES = ["spotfit_kernels.hip", "spotfit_group.hip", "spotfit_narrow.hip", "spotfit_init.hip",
+           "spotfit_plain.hip", "spotfit_api.hip",
            "spotfit_serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 OUT = os.path.join(HERE, "libspotfit.so")

@@ -28,6 +28,7 @@ struct spotfit_ctx {
   int occ_mixed[8];
   int32_t* ws;      // counters[8] then 3 lists of ws_cap spot indices
   int64_t ws_cap;
+  unsigned long long* stats;  // device histogram buffer of spotfit_get_stats
 };
 
 namespace {
@@ -52,6 +53,42 @@ int ppl_index(int ppl) {
     case 8: return 3;
     default: return 4;
   }
+}
+
+// spotfit_get_stats device buffer: n, status[6], iterations[65], grad, trial
+constexpr int kStatsLen = 1 + 6 + 65 + 2;
+
+__global__ void stats_zero_kernel(unsigned long long* buf) {
+  if (threadIdx.x < kStatsLen) buf[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void stats_kernel(const int32_t* status, const int32_t* iters,
+                                                     const int32_t* evals, int64_t n,
+                                                     unsigned long long* buf) {
+  __shared__ unsigned int hist[6 + 65];
+  __shared__ unsigned long long ev[2];
+  for (int i = threadIdx.x; i < 6 + 65; i += blockDim.x) hist[i] = 0u;
+  if (threadIdx.x < 2) ev[threadIdx.x] = 0ull;
+  __syncthreads();
+  unsigned long long gsum = 0, tsum = 0;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const int st = status[s];
+    if (st >= 0 && st < 6) atomicAdd(&hist[st], 1u);
+    const int it = iters[s];
+    atomicAdd(&hist[6 + (it < 0 ? 0 : it > 64 ? 64 : it)], 1u);
+    if (evals) {
+      gsum += (unsigned long long)(evals[2 * s] > 0 ? evals[2 * s] : 0);
+      tsum += (unsigned long long)(evals[2 * s + 1] > 0 ? evals[2 * s + 1] : 0);
+    }
+  }
+  if (gsum) atomicAdd(&ev[0], gsum);
+  if (tsum) atomicAdd(&ev[1], tsum);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 6 + 65; i += blockDim.x)
+    if (hist[i]) atomicAdd(&buf[1 + i], (unsigned long long)hist[i]);
+  if (threadIdx.x < 2 && ev[threadIdx.x]) atomicAdd(&buf[1 + 6 + 65 + threadIdx.x], ev[threadIdx.x]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) buf[0] = (unsigned long long)n;
 }
 
 }  // namespace
@@ -162,6 +199,12 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
   }
   c->ws = nullptr;
   c->ws_cap = 0;
+  c->stats = nullptr;
+  e = hipMalloc((void**)&c->stats, sizeof(unsigned long long) * kStatsLen);
+  if (e != hipSuccess) {
+    delete c;
+    return fail_hip(e, "hipMalloc (statistics buffer)");
+  }
   // default plan per size class (measured on MI355X), all narrow: <= 8 px side:
   // 4 lanes x 2 columns; <= 16: 4 lanes x 4 columns; <= 32: 16 lanes x 2 columns
   c->plan_for_class[0] = sf::wide_plan_count() + 0;
@@ -193,11 +236,12 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
 
 void spotfit_ctx_destroy(spotfit_ctx_t* ctx) {
   if (!ctx) return;
-  if (ctx->ws) {
+  if (ctx->ws || ctx->stats) {
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(ctx->device);
-    (void)hipFree(ctx->ws);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->stats) (void)hipFree(ctx->stats);
     if (cur >= 0) (void)hipSetDevice(cur);
   }
   delete ctx;
@@ -227,26 +271,37 @@ int spotfit_ctx_reserve(spotfit_ctx_t* ctx, int64_t n) {
   return SPOTFIT_OK;
 }
 
-int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
-                      const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
-                      int64_t n, const spotfit_options_t* opt, float* params_out,
-                      float* chi2_out, int32_t* iters_out, int32_t* status_out,
-                      int32_t* evals_out, void* stream) {
-  if (!ctx) return fail(SPOTFIT_E_NULL, "fit_spots: NULL context");
-  if (n < 0) return fail(SPOTFIT_E_ARG, "fit_spots: n_spots < 0");
-  if (dtype != SPOTFIT_U16 && dtype != SPOTFIT_F32) return fail(SPOTFIT_E_ARG, "fit_spots: unknown dtype");
-  spotfit_options_t o;
+}  // extern "C"
+
+namespace {
+
+// Checks of a fit call that need no HIP call; fills the validated options.
+int check_call(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
+               const int64_t* offsets, const float* init, int64_t n, const spotfit_options_t* opt,
+               float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
+               spotfit_options_t* o, const char* who) {
+  if (!ctx) return fail(SPOTFIT_E_NULL, (std::string(who) + ": NULL context").c_str());
+  if (n < 0) return fail(SPOTFIT_E_ARG, (std::string(who) + ": n_spots < 0").c_str());
+  if (dtype != SPOTFIT_U16 && dtype != SPOTFIT_F32)
+    return fail(SPOTFIT_E_ARG, (std::string(who) + ": unknown dtype").c_str());
   if (opt) {
-    o = *opt;
+    *o = *opt;
   } else {
-    spotfit_default_options(&o);
+    spotfit_default_options(o);
   }
-  int rc = spotfit_validate_options(&o);
+  int rc = spotfit_validate_options(o);
   if (rc != SPOTFIT_OK) return rc;
   if (n == 0) return SPOTFIT_OK;
   if (!data || !sizes || !offsets || !init || !params_out || !chi2_out || !iters_out || !status_out)
-    return fail(SPOTFIT_E_NULL, "fit_spots: NULL array");
+    return fail(SPOTFIT_E_NULL, (std::string(who) + ": NULL array").c_str());
+  return SPOTFIT_OK;
+}
 
+// Enqueue one fit with validated options o and n > 0.
+int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
+               const int64_t* offsets, const float* init, int64_t n, const spotfit_options_t& o,
+               float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
+               int32_t* evals_out, void* stream) {
   sf::KArgs ka;
   std::memset(&ka, 0, sizeof ka);
   ka.data = data;
@@ -305,6 +360,154 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
     e = sf::launch_wave_kernel(ppl, o.precision, ka, grid, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail_hip(e, "fit kernel launch");
+  return SPOTFIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                      const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
+                      int64_t n, const spotfit_options_t* opt, float* params_out,
+                      float* chi2_out, int32_t* iters_out, int32_t* status_out,
+                      int32_t* evals_out, void* stream) {
+  spotfit_options_t o;
+  int rc = check_call(ctx, data, dtype, sizes, offsets, init, n, opt, params_out, chi2_out,
+                      iters_out, status_out, &o, "fit_spots");
+  if (rc != SPOTFIT_OK || n == 0) return rc;
+  return launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
+                    status_out, evals_out, stream);
+}
+
+int spotfit_moment_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                        const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n,
+                        const spotfit_options_t* opt, float* init_out, void* stream) {
+  if (!ctx) return fail(SPOTFIT_E_NULL, "moment_init: NULL context");
+  if (n < 0) return fail(SPOTFIT_E_ARG, "moment_init: n_spots < 0");
+  if (dtype != SPOTFIT_U16 && dtype != SPOTFIT_F32) return fail(SPOTFIT_E_ARG, "moment_init: unknown dtype");
+  spotfit_options_t o;
+  if (opt) {
+    o = *opt;
+  } else {
+    spotfit_default_options(&o);
+  }
+  const int rc = spotfit_validate_options(&o);
+  if (rc != SPOTFIT_OK) return rc;
+  if (n == 0) return SPOTFIT_OK;
+  if (!data || !sizes || !offsets || !init_out) return fail(SPOTFIT_E_NULL, "moment_init: NULL array");
+  const hipError_t e = sf::launch_moment_init(data, dtype, sizes, offsets, n, o.max_side,
+                                              o.max_pixels, init_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "moment init kernel launch");
+  return SPOTFIT_OK;
+}
+
+int spotfit_get_stats(spotfit_ctx_t* ctx, const int32_t* status, const int32_t* iters,
+                      const int32_t* evals, int64_t n, spotfit_stats_t* out, void* stream) {
+  if (!ctx || !out) return fail(SPOTFIT_E_NULL, "get_stats: NULL context or output");
+  if (n < 0) return fail(SPOTFIT_E_ARG, "get_stats: n_spots < 0");
+  std::memset(out, 0, sizeof *out);
+  if (n == 0) return SPOTFIT_OK;
+  if (!status || !iters) return fail(SPOTFIT_E_NULL, "get_stats: NULL array");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(stats_zero_kernel, dim3(1), dim3(128), 0, st, ctx->stats);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_hip(e, "statistics kernel launch");
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(stats_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, st,
+                     status, iters, evals, n, ctx->stats);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail_hip(e, "statistics kernel launch");
+  unsigned long long h[kStatsLen];
+  e = hipMemcpyAsync(h, ctx->stats, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail_hip(e, "statistics copy");
+  out->n_spots = (int64_t)h[0];
+  for (int i = 0; i < 6; ++i) out->status_count[i] = (int64_t)h[1 + i];
+  for (int i = 0; i < 65; ++i) out->iters_hist[i] = (int64_t)h[7 + i];
+  out->grad_evals = (int64_t)h[72];
+  out->trial_evals = (int64_t)h[73];
+  return SPOTFIT_OK;
+}
+
+int spotfit_autotune(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                     const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
+                     int64_t n, const spotfit_options_t* opt, float* params_out, float* chi2_out,
+                     int32_t* iters_out, int32_t* status_out, int32_t reps,
+                     spotfit_tune_report_t* report, void* stream) {
+  spotfit_options_t o;
+  int rc = check_call(ctx, data, dtype, sizes, offsets, init, n, opt, params_out, chi2_out,
+                      iters_out, status_out, &o, "autotune");
+  if (rc != SPOTFIT_OK) return rc;
+  if (o.precision != SPOTFIT_PREC_FP64)
+    return fail(SPOTFIT_E_OPTIONS, "autotune: only the double-precision separable kernel has plans");
+  if (reps < 1) return fail(SPOTFIT_E_ARG, "autotune: reps < 1");
+  if (n == 0) return fail(SPOTFIT_E_ARG, "autotune: empty batch");
+  const bool mixed = o.schedule == SPOTFIT_SCHEDULE_MIXED;
+  const int cls = o.max_side <= 8 ? 0 : o.max_side <= 16 ? 1 : 2;
+  const int side = cls == 0 ? 8 : cls == 1 ? 16 : 32;
+  int cand[16];
+  int nc = 0;
+  if (mixed) {
+    for (int p = 0; p < sf::mixed_plan_count() && nc < 16; ++p) cand[nc++] = p;
+  } else {
+    for (int p = 0; p < sf::group_plan_count() && nc < 16; ++p) {
+      int L = 0, C = 0;
+      sf::group_plan_shape(p, &L, &C);
+      if (L * C >= side) cand[nc++] = p;
+    }
+  }
+  double ms[16];
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return fail_hip(e, "hipEventCreate");
+  const int keep = mixed ? ctx->mixed_plan : ctx->plan_for_class[cls];
+  int best = 0;
+  for (int i = 0; i < nc && rc == SPOTFIT_OK; ++i) {
+    if (mixed)
+      ctx->mixed_plan = cand[i];
+    else
+      ctx->plan_for_class[cls] = cand[i];
+    rc = launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
+                    status_out, nullptr, stream);
+    if (rc == SPOTFIT_OK && (e = hipEventRecord(e0, st)) != hipSuccess) rc = fail_hip(e, "hipEventRecord");
+    for (int r = 0; r < reps && rc == SPOTFIT_OK; ++r)
+      rc = launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out,
+                      iters_out, status_out, nullptr, stream);
+    if (rc == SPOTFIT_OK && (e = hipEventRecord(e1, st)) != hipSuccess) rc = fail_hip(e, "hipEventRecord");
+    if (rc == SPOTFIT_OK && (e = hipEventSynchronize(e1)) != hipSuccess) rc = fail_hip(e, "hipEventSynchronize");
+    float t = 0.f;
+    if (rc == SPOTFIT_OK && (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess)
+      rc = fail_hip(e, "hipEventElapsedTime");
+    ms[i] = double(t) / reps;
+    if (rc == SPOTFIT_OK && ms[i] < ms[best]) best = i;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int chosen = rc == SPOTFIT_OK ? cand[best] : keep;
+  if (mixed)
+    ctx->mixed_plan = chosen;
+  else
+    ctx->plan_for_class[cls] = chosen;
+  if (rc != SPOTFIT_OK) return rc;
+  // the outputs: the kept plan's results
+  rc = launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
+                  status_out, nullptr, stream);
+  if (rc != SPOTFIT_OK) return rc;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  if (report) {
+    std::memset(report, 0, sizeof *report);
+    report->schedule = o.schedule;
+    report->size_class = mixed ? -1 : cls;
+    report->n_candidates = nc;
+    report->chosen = best;
+    for (int i = 0; i < nc; ++i) {
+      report->plan_id[i] = cand[i];
+      report->plan_ms[i] = ms[i];
+    }
+  }
   return SPOTFIT_OK;
 }
 

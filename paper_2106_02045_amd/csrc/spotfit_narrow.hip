@@ -34,48 +34,14 @@
 
 #include "spotfit.h"
 #include "spotfit_internal.h"
+#include "lanegroup.h"
 #include "spotfit_lm.h"
-#include "xlane.h"
 
 namespace sf {
 namespace nrw {
 
 using namespace lm;
-
-// Total over the L lanes of a group (L consecutive lanes, L a power of two
-// <= 16): butterfly over lane bits 0 (quad_perm [1,0,3,2]), 1 (quad_perm
-// [2,3,0,1]), 2 (row_half_mirror) and 3 (row_mirror).
-template <int L>
-__device__ __forceinline__ double gsum(double v) {
-  if constexpr (L >= 2) v += dpp_mov<0xB1>(v);
-  if constexpr (L >= 4) v += dpp_mov<0x4E>(v);
-  if constexpr (L >= 8) v += dpp_mov<0x141>(v);
-  if constexpr (L >= 16) v += dpp_mov<0x140>(v);
-  return v;
-}
-
-// Value of in-group lane Q on every lane of the group.
-template <int L, int Q>
-__device__ __forceinline__ int gbcast_i(int v) {
-  if constexpr (L == 1) {
-    return v;
-  } else if constexpr (L == 2) {
-    return __builtin_amdgcn_mov_dpp(v, Q == 0 ? 0xA0 : 0xF5, 0xF, 0xF, true);
-  } else if constexpr (L == 4) {
-    return __builtin_amdgcn_mov_dpp(v, Q * 0x55, 0xF, 0xF, true);
-  } else {
-    // ds_swizzle bit-mask mode inside 32 lanes: lane' = (lane & and) | Q
-    constexpr int andm = L == 8 ? 0x18 : 0x10;
-    return __builtin_amdgcn_ds_swizzle(v, andm | (Q << 5));
-  }
-}
-
-template <int L, int Q>
-__device__ __forceinline__ double gbcast(double v) {
-  int2 u = *reinterpret_cast<int2*>(&v);
-  int2 r = make_int2(gbcast_i<L, Q>(u.x), gbcast_i<L, Q>(u.y));
-  return *reinterpret_cast<double*>(&r);
-}
+using namespace lg;
 
 // all[Q + L*j] = own[j] of in-group lane Q, for every Q < L.
 template <int L, int Q, int CPL, int HM>
@@ -463,15 +429,27 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
           da[j] = (Nn * dFG[j] - Gs * dF[j] - a * gam) * iD;
           db[j] = (Gs * dFF - FG * dF[j] - F * dFG[j] - b * gam) * iD;
         }
-        // normal matrix and right-hand side, J_j = da_j f + a df_j + db_j (Eq. 9, second factor)
+        // normal matrix, J_j = da_j f + a df_j + db_j (Eq. 9, second factor):
+        //   sum J_i J_j = da_i W_j + db_i Z_j + a (da_j Sfd_i + db_j dF_i) + a^2 sum df_i df_j
+        // with W_j = da_j FF + a Sfd_j + db_j F and Z_j = da_j F + a dF_j + N db_j
+        double W[4], Z[4], aS[4], aF[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          aS[j] = a * Sfd[j];
+          aF[j] = a * dF[j];
+          W[j] = __builtin_fma(da[j], FF, __builtin_fma(db[j], F, aS[j]));
+          Z[j] = __builtin_fma(da[j], F, __builtin_fma(db[j], Nn, aF[j]));
+        }
+        const double a2 = a * a;
         double M[10];
 #pragma unroll
         for (int t = 0; t < 10; ++t) {
           const int i = tri_i(t), j = tri_j(t);
-          const double Sdd = Xq[ox_of(i) + ox_of(j)] * Yq[oy_of(i) + oy_of(j)] * wt[i] * wt[j];
-          M[t] = da[i] * da[j] * FF + a * (da[i] * Sfd[j] + da[j] * Sfd[i]) +
-                 (da[i] * db[j] + db[i] * da[j]) * F + a * a * Sdd +
-                 a * (db[j] * dF[i] + db[i] * dF[j]) + Nn * db[i] * db[j];
+          const double Sdd = Xq[ox_of(i) + ox_of(j)] * Yq[oy_of(i) + oy_of(j)] * (wt[i] * wt[j]);
+          M[t] = __builtin_fma(da[i], W[j],
+                               __builtin_fma(db[i], Z[j],
+                                             __builtin_fma(da[j], aS[i],
+                                                           __builtin_fma(db[j], aF[i], a2 * Sdd))));
         }
         const double sfr = a * FF + b * F - FG;  // sum f r  (0 up to rounding, Eq. 4)
         const double sr = a * F + b * Nn - Gs;   // sum r

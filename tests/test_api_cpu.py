@@ -101,5 +101,51 @@ def test_call_level_errors_before_any_gpu_call():
     assert L.spotfit_ctx_reserve(fake, -1) == -2
 
 
+def test_stats_and_autotune_argument_errors():
+    L = sf.lib()
+    fake = ctypes.c_void_p(0x10)
+    st = sf.Stats()
+    assert L.spotfit_get_stats(None, 1, 1, None, 10, ctypes.byref(st), None) == -1
+    assert L.spotfit_get_stats(fake, 1, 1, None, 10, None, None) == -1
+    assert L.spotfit_get_stats(fake, 1, 1, None, -1, ctypes.byref(st), None) == -2
+    assert L.spotfit_get_stats(fake, None, None, None, 0, ctypes.byref(st), None) == 0
+    assert st.n_spots == 0 and sum(st.status_count) == 0
+    assert L.spotfit_get_stats(fake, None, 1, None, 5, ctypes.byref(st), None) == -1
+    o = sf.default_options()
+    rep = sf.TuneReport()
+    args = (1, 0, 1, 1, 1, 10, ctypes.byref(o), 1, 1, 1, 1)
+    assert L.spotfit_autotune(None, *args, 3, ctypes.byref(rep), None) == -1
+    assert L.spotfit_autotune(fake, *args, 0, ctypes.byref(rep), None) == -2
+    assert L.spotfit_autotune(fake, 1, 0, 1, 1, 1, 0, ctypes.byref(o), 1, 1, 1, 1, 3,
+                              ctypes.byref(rep), None) == -2
+    p32 = sf.default_options(precision=sf.PREC_FP32)
+    assert L.spotfit_autotune(fake, 1, 0, 1, 1, 1, 10, ctypes.byref(p32), 1, 1, 1, 1, 3,
+                              ctypes.byref(rep), None) == -3
+
+
+def test_stats_and_report_struct_layout_matches_header():
+    import subprocess
+    import tempfile
+    checks = [("spotfit_stats_t", sf.Stats), ("spotfit_tune_report_t", sf.TuneReport)]
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "p.c")
+        body = ""
+        for cname, cls in checks:
+            for f, _ in cls._fields_:
+                body += f'printf("%zu ", offsetof({cname}, {f}));'
+            body += f'printf("%zu ", sizeof({cname}));'
+        with open(src, "w") as fh:
+            fh.write('#include <stdio.h>\n#include <stddef.h>\n#include "spotfit.h"\n'
+                     f'int main(void){{{body} return 0;}}\n')
+        exe = os.path.join(d, "p")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
+                                              check=True).stdout.split()]
+    want = []
+    for _, cls in checks:
+        want += [getattr(cls, f).offset for f, _ in cls._fields_] + [ctypes.sizeof(cls)]
+    assert out == want
+
+
 def test_version():
     assert sf.version() >= 100

@@ -235,3 +235,56 @@ def test_per_pixel_kernels_within_tolerance(gpu, prec):
     assert c["max_dxy"] < 1e-3
     assert c["tol_fail_same"] <= (0 if prec != 3 else 0.01 * b.n)
     assert c["status_mismatch"] <= 0.1 * b.n
+
+
+def _tensors(b):
+    import torch
+    dev = torch.device("cuda:0")
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    return up(b.data), up(b.sizes), up(b.offsets), up(b.init)
+
+
+def test_stats_summarise_the_outputs():
+    import torch
+
+    import paper_2106_02045_amd as sf
+    ctx = sf.Context(0)
+    b = spotgen.config(3, n=20000)
+    out = ctx.fit_spots(*_tensors(b), sf.default_options(), want_evals=True)
+    st = ctx.stats(out)
+    torch.cuda.synchronize()
+    status = out["status"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    evals = out["evals"].cpu().numpy()
+    assert st["n_spots"] == b.n
+    assert st["status_count"] == np.bincount(status, minlength=6).tolist()
+    assert st["iters_hist"] == np.bincount(np.minimum(iters, 64), minlength=65).tolist()
+    assert st["grad_evals"] == int(evals[:, 0].sum()) and st["trial_evals"] == int(evals[:, 1].sum())
+    # without evaluation counts
+    out.pop("evals")
+    st2 = ctx.stats(out)
+    assert st2["grad_evals"] == 0 and st2["status_count"] == st["status_count"]
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_autotune_keeps_a_plan_and_stays_exact(schedule):
+    import torch
+
+    import paper_2106_02045_amd as sf
+    ctx = sf.Context(0)
+    b = spotgen.config(0)
+    o = sf.default_options(max_side=16, schedule=schedule)
+    t = _tensors(b)
+    out, rep = ctx.autotune(*t, o, reps=2)
+    torch.cuda.synchronize()
+    assert len(rep["plan_id"]) >= 2 and rep["chosen_plan"] in rep["plan_id"]
+    assert all(ms > 0 for ms in rep["plan_ms"])
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    r = oracle.fit_batch(b, oracle.default_opts(), threads=8)
+    c = compare(g, r, chi_band=CHI_BAND, step_band=STEP_BAND)
+    assert c["strict_mismatch"] == 0 and c["status_mismatch"] == 0
+    # later calls on the context use the kept plan: identical bits
+    again = ctx.fit_spots(*t, o)
+    torch.cuda.synchronize()
+    for k in ("params", "chi2", "iters", "status"):
+        np.testing.assert_array_equal(again[k].cpu().numpy(), g[k])

@@ -332,3 +332,66 @@ def test_fig8_iteration_and_stop_statistics():
     assert st[oracle.MAX_ITER] < 0.005
     # double precision keeps MinStep rare, though above the paper's single-precision < 1 %
     assert st[oracle.MIN_STEP] < 0.1
+
+
+# ---------------------------------------------------------------------------
+# Start values (centroid / second moments): outside the paper's method, pinned
+# by hand-built images whose estimate is known exactly.
+# ---------------------------------------------------------------------------
+def test_moment_init_single_bright_pixel():
+    g = np.full((9, 11), 100.0)
+    g[4, 3] = 500.0
+    out = oracle.moment_init(g, 11, 9, 0)
+    np.testing.assert_array_equal(out, [3.0, 4.0, 0.8, 0.8])  # zero spread, clamped to 0.8
+
+
+def test_moment_init_flat_image_falls_back_to_roi_centre():
+    out = oracle.moment_init(np.full((7, 9), 42.0), 9, 7, 1)
+    np.testing.assert_array_equal(out, [4.0, 3.0, 1.5, 1.5])
+
+
+def test_moment_init_known_moments():
+    # background 50 everywhere; +100 at (x +- 3, y) and (x, y +- 1) around (5, 5):
+    # centroid (5, 5), var_x = 2*9*100/400 = 4.5, var_y = 2*1*100/400 = 0.5
+    g = np.full((11, 11), 50.0)
+    for (r, c) in [(5, 2), (5, 8), (4, 5), (6, 5)]:
+        g[r, c] = 150.0
+    sym = oracle.moment_init(g, 11, 11, 0)
+    ell = oracle.moment_init(g, 11, 11, 1)
+    np.testing.assert_allclose(sym, [5.0, 5.0, np.sqrt(2.5), np.sqrt(2.5)], rtol=1e-15)
+    np.testing.assert_allclose(ell, [5.0, 5.0, np.sqrt(4.5), 0.8], rtol=1e-15)  # sigma_y clamped
+
+
+def test_moment_init_ring_median_is_mean_of_middle_values():
+    # 9x9 ring of 32 pixels: 16 at 10 and 16 at 20, the 20s placed symmetrically
+    # (odd columns of the top and bottom rows, odd rows of the side columns), so
+    # b0 = 15 and the ring's own weights (5 each) centre on (4, 4).  Interior 0
+    # except 25 at (x=3, y=4) and 45 at (x=5, y=4): weights 10 and 30, so
+    # cx = (80*4 + 10*3 + 30*5) / 120; b0 = 10 or 20 would give 860/210 or 140/30
+    w = h = 9
+    g = np.zeros((h, w))
+    for c in range(w):
+        g[0, c] = g[h - 1, c] = 20.0 if c % 2 else 10.0
+    for r in range(1, h - 1):
+        g[r, 0] = g[r, w - 1] = 20.0 if r % 2 else 10.0
+    g[4, 3] = 25.0
+    g[4, 5] = 45.0
+    out = oracle.moment_init(g, w, h, 0)
+    assert out[0] == pytest.approx(500.0 / 120.0, rel=1e-15) and out[1] == 4.0
+
+
+def test_moment_init_matches_the_vectorised_estimate():
+    # an independent (numpy, vectorised) implementation of the same estimate
+    for name in ("small_11x11", "mixed_7to32", "precision_32x32_ell"):
+        b = spotgen.workload(name, n=600)
+        mine = oracle.moment_init_batch(b)
+        for s in range(0, b.n, 7):
+            w, h, model = int(b.sizes[s, 0]), int(b.sizes[s, 1]), int(b.sizes[s, 2])
+            img = b.spot(s).reshape(1, h, w).astype(np.float64)
+            ref = spotgen.moment_init(img, model)[0]
+            np.testing.assert_allclose(mine[s], ref, rtol=1e-12, atol=1e-12)
+
+
+def test_moment_init_rejects_unusable_shapes():
+    assert np.all(np.isnan(oracle.moment_init(np.ones(6), 2, 3, 0)))
+    assert np.all(np.isnan(oracle.moment_init(np.ones(25), 5, 5, 7)))
