@@ -242,7 +242,8 @@ typedef struct spotfit_serve spotfit_serve_t; /* opaque */
 typedef struct {
   const void* data;              /* n_spots spots of pixels, dtype below              */
   const spotfit_shape_t* sizes;  /* n_spots shapes                                     */
-  const float* init;             /* n_spots x 4 start values                           */
+  const float* init;             /* n_spots x 4 start values, or NULL: computed on the
+                                    device as by spotfit_moment_init                   */
   int32_t n_spots;
   int32_t dtype;                 /* spotfit_dtype_t                                    */
   float* params_out;             /* n_spots x 6                                        */

@@ -355,15 +355,18 @@ class Server:
 
     @staticmethod
     def make_frame(data, sizes, init):
-        """Build a spotfit_frame_t (and its output arrays) from numpy arrays."""
+        """Build a spotfit_frame_t (and its output arrays) from numpy arrays.
+        init None: start values computed on the device."""
         import numpy as np
         data = np.ascontiguousarray(data)
         sizes = np.ascontiguousarray(sizes, dtype=np.uint8)
-        init = np.ascontiguousarray(init, dtype=np.float32)
+        if init is not None:
+            init = np.ascontiguousarray(init, dtype=np.float32)
         n = int(sizes.shape[0])
         outs = dict(params=np.zeros((n, 6), np.float32), chi2=np.zeros(n, np.float32),
                     iters=np.zeros(n, np.int32), status=np.zeros(n, np.int32))
-        f = Frame(data.ctypes.data, sizes.ctypes.data, init.ctypes.data, n,
+        f = Frame(data.ctypes.data, sizes.ctypes.data,
+                  init.ctypes.data if init is not None else None, n,
                   U16 if data.dtype == np.uint16 else F32, outs["params"].ctypes.data,
                   outs["chi2"].ctypes.data, outs["iters"].ctypes.data, outs["status"].ctypes.data)
         return f, (data, sizes, init), outs

@@ -54,8 +54,11 @@ __device__ __forceinline__ void gather_rows(const double (&own)[CPL], double (&a
 }
 
 // Zeros that the loads of a column outside a spot read instead (one row offset
-// of a 32 x 32 spot at most, as float or as 16-bit values).
-__device__ const float kZeros[32 * 32] = {};
+// of a 32 x 32 spot at most, as float or as 16-bit values).  Never written.  Not
+// const: a constant-memory array would make its pointer and the pixel pointer
+// meet in the generic address space, turning every pixel load into a FLAT load
+// (which also holds up every later LDS wait).
+__device__ float kZeros[32 * 32];
 
 // Spots s = base + group, then + stride, ... of a uniform batch.
 struct StridedSrc {
@@ -96,9 +99,19 @@ struct NState {
   double Sx, Sxx, Sy, Syy, FG, D, Bx, Bsx, By, Bsy;
 };
 
+// Pixel value of a stored 32-bit pattern: a 16-bit count, or a float.
+template <int DT>
+__device__ __forceinline__ double pixel(uint32_t v) {
+  if constexpr (DT == SPOTFIT_U16)
+    return double(v);
+  else
+    return double(__uint_as_float(v));
+}
+
 // Fit every spot the source hands to this wavefront's groups.
-// L lanes per spot, CPL columns per lane: spots with w, h <= L * CPL.
-template <int L, int CPL, class Src>
+// L lanes per spot, CPL columns per lane: spots with w, h <= L * CPL; pixel
+// data type DT (SPOTFIT_U16 or SPOTFIT_F32).
+template <int L, int CPL, int DT, class Src>
 __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NState* sts) {
   constexpr int HM = L * CPL;
   const int lane = __lane_id();
@@ -107,11 +120,13 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
   const KOpts o = ka.opt;
   const double tau = o.tie_tau;
 
-  int64_t s = src.first(gi, li);
+  int64_t s = -1;  // the group's current spot
   int w = 0, h = 0, k = 0, it = 0, status = 0, mode = kNew, n_grad = 0, n_trial = 0;
   bool sym = true, small = false;
 
-  float g[CPL][HM];          // pixels of the lane's columns (0 outside the spot)
+  // pixels of the lane's columns as loaded (0 outside the spot); converted where
+  // used, so that no instruction of the fetch waits for the loads
+  uint32_t g[CPL][HM];
   double ex[CPL], eyl[CPL];  // column factors of its columns, row factors of its rows
   double pc[4] = {0.0, 0.0, 0.0, 0.0};  // candidate point (accepted point after a decision)
   double a = 0.0, b = 0.0, chi = 0.0;   // Eq. 6 amplitudes and Eq. 2 error at pc
@@ -123,12 +138,34 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
   // ever reads back its own writes: no synchronisation is needed.
   NState& S = sts[gi];
 
-  // Fetch the next spot of this group, writing BAD_INPUT for unusable ones.
-  auto fetch = [&]() {
-    while (s >= 0) {
-      const spotfit_shape_t sh = ka.sizes[s];
-      const float* in = ka.init + 4 * s;
-      const float i0 = in[0], i1 = in[1], i2 = in[2], i3 = in[3];
+  // The next spot's description is loaded one spot ahead, so that a fetch can
+  // issue the pixel loads at once; nothing in the fetch uses a loaded pixel, so
+  // the loads complete behind the rest of the wave step.
+  int64_t ns = src.first(gi, li);
+  spotfit_shape_t nsh{0, 0, 0, 0};
+  int64_t noff = 0;
+  float4 nin = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto prefetch = [&]() {
+    if (ns >= 0) {
+      nsh = ka.sizes[ns];
+      noff = ka.offsets[ns];
+      const float* in = ka.init + 4 * ns;
+      nin = make_float4(in[0], in[1], in[2], in[3]);
+    }
+  };
+  prefetch();
+
+  // Take the next spot of this group (its description only), writing
+  // BAD_INPUT for unusable ones.
+  int64_t off = 0;  // element offset of the current spot's pixels
+  auto advance = [&]() {
+    while (ns >= 0) {
+      s = ns;
+      const spotfit_shape_t sh = nsh;
+      const float i0 = nin.x, i1 = nin.y, i2 = nin.z, i3 = nin.w;
+      off = noff;
+      ns = src.next(s, li);
+      prefetch();
       const int mdl = sh.model;
       const bool ell = mdl == SPOTFIT_ELL;
       const bool bad = sh.w < 3 || sh.h < 3 || sh.w > HM || sh.h > HM ||
@@ -144,53 +181,6 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
         pc[1] = i1;
         pc[2] = i2;
         pc[3] = ell ? (double)i3 : (double)i2;
-        const int64_t off = ka.offsets[s];
-        // Every slot of the lane's columns is loaded at once, with no predicated
-        // load: a column outside the spot reads a block of zeros, a row below it
-        // repeats the spot's last row (every pass skips rows >= h).
-        double cs = 0.0;
-        if (ka.dtype == SPOTFIT_U16) {
-          const uint16_t* zero = reinterpret_cast<const uint16_t*>(kZeros);
-          const uint16_t* cp[CPL];  // top of each of the lane's columns
-#pragma unroll
-          for (int j = 0; j < CPL; ++j)
-            cp[j] = li + L * j < w ? static_cast<const uint16_t*>(ka.data) + off + li + L * j : zero;
-          uint32_t csi = 0;  // sum of the spot's pixels in the lane's columns (exact)
-#pragma unroll
-          for (int r = 0; r < HM; ++r) {
-            const uint32_t ro = uint32_t(r < h ? r : h - 1) * uint32_t(w);
-            uint32_t rs = 0;
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) {
-              const uint32_t v = cp[j][ro];
-              g[j][r] = float(v);
-              rs += v;
-            }
-            csi += r < h ? rs : 0u;
-          }
-          cs = double(csi);
-        } else {
-          const float* zero = kZeros;
-          const float* cp[CPL];
-#pragma unroll
-          for (int j = 0; j < CPL; ++j)
-            cp[j] = li + L * j < w ? static_cast<const float*>(ka.data) + off + li + L * j : zero;
-          double csj[CPL];
-#pragma unroll
-          for (int j = 0; j < CPL; ++j) csj[j] = 0.0;
-#pragma unroll
-          for (int r = 0; r < HM; ++r) {
-            const uint32_t ro = uint32_t(r < h ? r : h - 1) * uint32_t(w);
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) {
-              g[j][r] = cp[j][ro];
-              csj[j] += r < h ? double(g[j][r]) : 0.0;
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < CPL; ++j) cs += csj[j];
-        }
-        Gs = gsum<L>(cs);
         Tme = o.max_error_per_px * double(w * h);
         k = o.lambda0_exp10;
         it = 0;
@@ -211,11 +201,47 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
           ka.evals_out[2 * s + 1] = 0;
         }
       }
-      s = src.next(s, li);
+    }
+    s = -1;
+  };
+
+  // The current spot's pixels into g, every slot at once and with no predicated
+  // load: a column outside the spot reads a block of zeros, a row below it
+  // repeats the spot's last row (every pass skips rows >= h).  Every wave step
+  // reloads them (a spot that stays is read again from the cache), so that g
+  // is never merged with an older value: no instruction waits for these loads
+  // before the next trial evaluation reads them.
+  auto load_pixels = [&]() {
+    const int hh = h > 0 ? h : 1;
+    if constexpr (DT == SPOTFIT_U16) {
+      const uint16_t* zero = reinterpret_cast<const uint16_t*>(kZeros);
+      const uint16_t* cp[CPL];  // top of each of the lane's columns
+#pragma unroll
+      for (int j = 0; j < CPL; ++j)
+        cp[j] = li + L * j < w ? static_cast<const uint16_t*>(ka.data) + off + li + L * j : zero;
+#pragma unroll
+      for (int r = 0; r < HM; ++r) {
+        const uint32_t ro = uint32_t(r < hh ? r : hh - 1) * uint32_t(w);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) g[j][r] = cp[j][ro];
+      }
+    } else {
+      const uint32_t* zero = reinterpret_cast<const uint32_t*>(kZeros);
+      const uint32_t* cp[CPL];
+#pragma unroll
+      for (int j = 0; j < CPL; ++j)
+        cp[j] = li + L * j < w ? static_cast<const uint32_t*>(ka.data) + off + li + L * j : zero;
+#pragma unroll
+      for (int r = 0; r < HM; ++r) {
+        const uint32_t ro = uint32_t(r < hh ? r : hh - 1) * uint32_t(w);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) g[j][r] = cp[j][ro];
+      }
     }
   };
 
-  fetch();
+  advance();
+  load_pixels();
 
   while (__builtin_amdgcn_ballot_w64(s >= 0) != 0) {
     if (s >= 0) {
@@ -243,7 +269,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
         double t[CPL];
 #pragma unroll
         for (int j = 0; j < CPL; ++j) t[j] = 0.0;
-        double gp = 0.0, byp = 0.0, bsyp = 0.0;
+        double gp = 0.0, byp = 0.0, bsyp = 0.0, gsum_px = 0.0;
 #pragma unroll
         for (int r = 0; r < HM; ++r) {
           if (r < h) {
@@ -251,9 +277,10 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
             double sr = 0.0;
 #pragma unroll
             for (int j = 0; j < CPL; ++j) {
-              const double gd = double(g[j][r]);
+              const double gd = pixel<DT>(g[j][r]);
               t[j] = __builtin_fma(gd, e, t[j]);
               sr = __builtin_fma(gd, ex[j], sr);
+              gsum_px += gd;
             }
             const double dyr = double(r) - y;
             const double es = e * sr;
@@ -270,6 +297,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
           bxp = __builtin_fma(dx, et, bxp);
           bsxp = __builtin_fma(dx * dx, et, bsxp);
         }
+        if (mode == kNew) Gs = gsum<L>(gsum_px);  // sum g of a new spot (exact for 16-bit data)
         const double Sx = gsum<L>(sxp), Sxx = gsum<L>(sxxp);
         const double Sy = gsum<L>(syp), Syy = gsum<L>(syyp);
         const double FG = gsum<L>(gp);
@@ -306,9 +334,9 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
             for (int j = 0; j < CPL; ++j) {
               // a fresh conversion: reusing the first pass's doubles would keep
               // all CPL*HM of them live in registers
-              float gv = g[j][r];
+              uint32_t gv = g[j][r];
               asm("" : "+v"(gv));
-              const double res = __builtin_fma(aex[j], e, bm[j] - double(gv));
+              const double res = __builtin_fma(aex[j], e, bm[j] - pixel<DT>(gv));
               c2[j] = __builtin_fma(res, res, c2[j]);
             }
           }
@@ -377,6 +405,37 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
         }
       }
 
+      // ================= results and the next spot =================
+      if (done) {
+        if (li == 0) {
+          float* po = ka.params_out + 6 * s;
+          if (out_best) {
+            po[0] = float(S.best[0]);
+            po[1] = float(S.best[1]);
+            po[2] = float(S.best[2]);
+            po[3] = float(S.best[3]);
+            po[4] = float(S.a_best);
+            po[5] = float(S.b_best);
+            ka.chi2_out[s] = float(S.chi_best);
+          } else {
+            po[0] = float(pc[0]);
+            po[1] = float(pc[1]);
+            po[2] = float(pc[2]);
+            po[3] = float(pc[3]);
+            po[4] = float(a);
+            po[5] = float(b);
+            ka.chi2_out[s] = float(chi);
+          }
+          ka.iters_out[s] = it;
+          ka.status_out[s] = status;
+          if (ka.evals_out) {
+            ka.evals_out[2 * s] = n_grad;
+            ka.evals_out[2 * s + 1] = n_trial;
+          }
+        }
+        advance();
+      }
+
       // ================= derivative pass at pc (Eqs. 7-9, 11) =================
       if (do_grad) {
         const double x = pc[0], y = pc[1];
@@ -416,67 +475,50 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
         const double Nn = double(w * h), iD = rcp_nr(S.D);
         const double F = Sx * Sy, FF = Sxx * Syy;
         const double wt[4] = {isx * isx, isy * isy, isx * isx * isx, isy * isy * isy};
-        // Eq. 7 sums of parameter j and Eq. 8 amplitude derivatives
-        double dF[4], Sfd[4], dFG[4], da[4], db[4];
+        // Eq. 7 sums of parameter j, Eq. 8 amplitude derivatives, and the right-hand
+        // side; the normal matrix, with J_j = da_j f + a df_j + db_j (Eq. 9, second
+        // factor), is
+        //   sum J_i J_j = da_i W_j + db_i Z_j + a (da_j Sfd_i + db_j dF_i) + a^2 sum df_i df_j
+        // with W_j = da_j FF + a Sfd_j + db_j F and Z_j = da_j F + a dF_j + N db_j
+        const double sfr = a * FF + b * F - FG;  // sum f r  (0 up to rounding, Eq. 4)
+        const double sr = a * F + b * Nn - Gs;   // sum r
+        double da[4], db[4], W[4], Z[4], aS[4], aF[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int ox = ox_of(j), oy = oy_of(j);
-          dF[j] = X[ox] * Y[oy] * wt[j];
-          Sfd[j] = Xq[ox] * Yq[oy] * wt[j];
-          dFG[j] = Bj[j] * wt[j];
-          const double dFF = 2.0 * Sfd[j];
-          const double gam = Nn * dFF - 2.0 * F * dF[j];
-          da[j] = (Nn * dFG[j] - Gs * dF[j] - a * gam) * iD;
-          db[j] = (Gs * dFF - FG * dF[j] - F * dFG[j] - b * gam) * iD;
-        }
-        // normal matrix, J_j = da_j f + a df_j + db_j (Eq. 9, second factor):
-        //   sum J_i J_j = da_i W_j + db_i Z_j + a (da_j Sfd_i + db_j dF_i) + a^2 sum df_i df_j
-        // with W_j = da_j FF + a Sfd_j + db_j F and Z_j = da_j F + a dF_j + N db_j
-        double W[4], Z[4], aS[4], aF[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          aS[j] = a * Sfd[j];
-          aF[j] = a * dF[j];
+          const double dF = X[ox] * Y[oy] * wt[j];
+          const double Sfd = Xq[ox] * Yq[oy] * wt[j];
+          const double dFG = Bj[j] * wt[j];
+          const double dFF = 2.0 * Sfd;
+          const double gam = Nn * dFF - 2.0 * F * dF;
+          da[j] = (Nn * dFG - Gs * dF - a * gam) * iD;
+          db[j] = (Gs * dFF - FG * dF - F * dFG - b * gam) * iD;
+          aS[j] = a * Sfd;
+          aF[j] = a * dF;
           W[j] = __builtin_fma(da[j], FF, __builtin_fma(db[j], F, aS[j]));
           Z[j] = __builtin_fma(da[j], F, __builtin_fma(db[j], Nn, aF[j]));
+          S.bv[j] = -(da[j] * sfr + a * (a * Sfd + b * dF - dFG) + db[j] * sr);
         }
         const double a2 = a * a;
-        double M[10];
 #pragma unroll
         for (int t = 0; t < 10; ++t) {
           const int i = tri_i(t), j = tri_j(t);
           const double Sdd = Xq[ox_of(i) + ox_of(j)] * Yq[oy_of(i) + oy_of(j)] * (wt[i] * wt[j]);
-          M[t] = __builtin_fma(da[i], W[j],
-                               __builtin_fma(db[i], Z[j],
-                                             __builtin_fma(da[j], aS[i],
-                                                           __builtin_fma(db[j], aF[i], a2 * Sdd))));
+          S.A[t] = __builtin_fma(da[i], W[j],
+                                 __builtin_fma(db[i], Z[j],
+                                               __builtin_fma(da[j], aS[i],
+                                                             __builtin_fma(db[j], aF[i], a2 * Sdd))));
         }
-        const double sfr = a * FF + b * F - FG;  // sum f r  (0 up to rounding, Eq. 4)
-        const double sr = a * F + b * Nn - Gs;   // sum r
-        double rhs[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          rhs[j] = -(da[j] * sfr + a * (a * Sfd[j] + b * dF[j] - dFG[j]) + db[j] * sr);
         if (sym) {  // sigma = sx = sy: contract along d/dsigma = d/dsx + d/dsy, pad with identity
-          S.A[0] = M[0];
-          S.A[1] = M[1];
-          S.A[2] = M[2] + M[3];
+          S.A[2] += S.A[3];
           S.A[3] = 0.0;
-          S.A[4] = M[4];
-          S.A[5] = M[5] + M[6];
+          S.A[5] += S.A[6];
           S.A[6] = 0.0;
-          S.A[7] = M[7] + 2.0 * M[8] + M[9];
+          S.A[7] += 2.0 * S.A[8] + S.A[9];
           S.A[8] = 0.0;
           S.A[9] = 1.0;
-          S.bv[0] = rhs[0];
-          S.bv[1] = rhs[1];
-          S.bv[2] = rhs[2] + rhs[3];
+          S.bv[2] += S.bv[3];
           S.bv[3] = 0.0;
-        } else {
-#pragma unroll
-          for (int t = 0; t < 10; ++t) S.A[t] = M[t];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) S.bv[j] = rhs[j];
         }
       }
 
@@ -496,53 +538,25 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
                 (sym || fabs(d[3]) < o.min_step_rel * fabs(b3));
       }
 
-      // ================= results and the next spot =================
-      if (done) {
-        if (li == 0) {
-          float* po = ka.params_out + 6 * s;
-          if (out_best) {
-            po[0] = float(S.best[0]);
-            po[1] = float(S.best[1]);
-            po[2] = float(S.best[2]);
-            po[3] = float(S.best[3]);
-            po[4] = float(S.a_best);
-            po[5] = float(S.b_best);
-            ka.chi2_out[s] = float(S.chi_best);
-          } else {
-            po[0] = float(pc[0]);
-            po[1] = float(pc[1]);
-            po[2] = float(pc[2]);
-            po[3] = float(pc[3]);
-            po[4] = float(a);
-            po[5] = float(b);
-            ka.chi2_out[s] = float(chi);
-          }
-          ka.iters_out[s] = it;
-          ka.status_out[s] = status;
-          if (ka.evals_out) {
-            ka.evals_out[2 * s] = n_grad;
-            ka.evals_out[2 * s + 1] = n_trial;
-          }
-        }
-        s = src.next(s, li);
-        fetch();
-      }
+      // pixels for the next step's evaluation (the next spot's after a fetch)
+      load_pixels();
+
     }
   }
 }
 
-template <int L, int CPL, int WPE>
+template <int L, int CPL, int WPE, int DT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_narrow_kernel(KArgs ka) {
   constexpr int G = 64 / L;
   __shared__ NState sts[G];
   const StridedSrc src{ka.n, (int64_t)blockIdx.x * G, (int64_t)gridDim.x * G};
-  fit_narrow<L, CPL>(ka, src, sts);
+  fit_narrow<L, CPL, DT>(ka, src, sts);
 }
 
 // Batches of uneven spot sizes: the classify pass of the wide kernel's mixed
 // launch buckets spots by size class; each wavefront runs the plan of one class
 // and moves on to the next class when that class's list runs dry.
-template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE>
+template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE, int DT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_narrow_mixed_kernel(
     KArgs ka, MixedWs ws) {
   __shared__ NState sts[64 / L0];
@@ -554,11 +568,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     int32_t* take = ws.counters + 3 + c;
     const int32_t count = ws.counters[c];
     if (c == 0)
-      fit_narrow<L0, C0>(ka, QueueSrc<L0>{list, take, count}, sts);
+      fit_narrow<L0, C0, DT>(ka, QueueSrc<L0>{list, take, count}, sts);
     else if (c == 1)
-      fit_narrow<L1, C1>(ka, QueueSrc<L1>{list, take, count}, sts);
+      fit_narrow<L1, C1, DT>(ka, QueueSrc<L1>{list, take, count}, sts);
     else
-      fit_narrow<L2, C2>(ka, QueueSrc<L2>{list, take, count}, sts);
+      fit_narrow<L2, C2, DT>(ka, QueueSrc<L2>{list, take, count}, sts);
   }
 }
 
@@ -588,7 +602,7 @@ void narrow_plan_shape(int plan, int* lanes, int* cpl) {
 
 const void* narrow_kernel_symbol(int plan) {
 #define SF_NSYM(I, L, C, W) \
-  if (plan == I) return reinterpret_cast<const void*>(&nrw::fit_narrow_kernel<L, C, W>);
+  if (plan == I) return reinterpret_cast<const void*>(&nrw::fit_narrow_kernel<L, C, W, SPOTFIT_U16>);
   SF_NARROW_PLANS(SF_NSYM)
 #undef SF_NSYM
   return nullptr;
@@ -603,7 +617,7 @@ int narrow_mixed_plan_count() { return 1; }
 const void* narrow_mixed_kernel_symbol(int plan) {
 #define SF_NMSYM(I, A, B, C, D, E, F, W) \
   if (plan == I)                         \
-    return reinterpret_cast<const void*>(&nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W>);
+    return reinterpret_cast<const void*>(&nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_U16>);
   SF_NARROW_MIXED_PLANS(SF_NMSYM)
 #undef SF_NMSYM
   return nullptr;
@@ -611,10 +625,14 @@ const void* narrow_mixed_kernel_symbol(int plan) {
 
 hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid,
                                    hipStream_t st) {
-#define SF_NMLAUNCH(I, A, B, C, D, E, F, W)                                                    \
-  if (plan == I) {                                                                             \
-    hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W>), dim3(grid), dim3(64), \
-                       0, st, ka, ws);                                                         \
+#define SF_NMLAUNCH(I, A, B, C, D, E, F, W)                                                      \
+  if (plan == I) {                                                                               \
+    if (ka.dtype == SPOTFIT_U16)                                                                 \
+      hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_U16>),       \
+                         dim3(grid), dim3(64), 0, st, ka, ws);                                   \
+    else                                                                                         \
+      hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_F32>),       \
+                         dim3(grid), dim3(64), 0, st, ka, ws);                                   \
     return hipGetLastError();                                                                  \
   }
   SF_NARROW_MIXED_PLANS(SF_NMLAUNCH)
@@ -623,9 +641,14 @@ hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws,
 }
 
 hipError_t launch_narrow_kernel(int plan, const KArgs& ka, int grid, hipStream_t st) {
-#define SF_NLAUNCH(I, L, C, W)                                                               \
-  if (plan == I) {                                                                           \
-    hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W>), dim3(grid), dim3(64), 0, st, ka); \
+#define SF_NLAUNCH(I, L, C, W)                                                                \
+  if (plan == I) {                                                                            \
+    if (ka.dtype == SPOTFIT_U16)                                                              \
+      hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W, SPOTFIT_U16>), dim3(grid), dim3(64), \
+                         0, st, ka);                                                          \
+    else                                                                                      \
+      hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W, SPOTFIT_F32>), dim3(grid), dim3(64), \
+                         0, st, ka);                                                          \
     return hipGetLastError();                                                                \
   }
   SF_NARROW_PLANS(SF_NLAUNCH)

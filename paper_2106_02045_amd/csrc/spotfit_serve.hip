@@ -46,6 +46,7 @@ struct FrameRec {
   uint64_t ticket = 0;
   int state = kFree;
   int dtype = 0;
+  bool dev_init = false;   // start values computed on the device
   int64_t n = 0;           // spots
   int64_t spot0 = 0;       // first index in the spot ring
   int64_t pix_off = 0;     // byte offset in the pixel ring
@@ -151,6 +152,7 @@ bool spotfit_serve::launch_ready() {
   uint64_t t0, t1;
   int64_t spot0, nsp = 0;
   int dtype;
+  bool dev_init = false;
   // nothing new to launch, or no stream free: return without taking the lock
   if (next_launch >= admitted_end.load(std::memory_order_acquire)) return false;
   {
@@ -170,15 +172,18 @@ bool spotfit_serve::launch_ready() {
         break;
       }
     if (si < 0) return false;
-    // the batch: consecutive admitted frames of one dtype that are contiguous in
-    // the spot ring
+    // the batch: consecutive admitted frames of one dtype and one source of
+    // start values that are contiguous in the spot ring
     t0 = next_launch;
     spot0 = f0.spot0;
     dtype = f0.dtype;
+    dev_init = f0.dev_init;
     t1 = t0;
     while (t1 < next_ticket) {
       FrameRec& f = rec(t1);
-      if (f.state != kAdmitted || f.dtype != dtype || f.spot0 != spot0 + nsp) break;
+      if (f.state != kAdmitted || f.dtype != dtype || f.dev_init != dev_init ||
+          f.spot0 != spot0 + nsp)
+        break;
       nsp += f.n;
       ++t1;
     }
@@ -215,11 +220,14 @@ bool spotfit_serve::launch_ready() {
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_offs + spot0, h_offs + spot0, sizeof(int64_t) * nsp, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
+  int rc = SPOTFIT_OK;
+  if (e == hipSuccess && dev_init)
+    rc = spotfit_moment_init(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0, nsp, &opt,
+                             d_init + 4 * spot0, st);
+  else if (e == hipSuccess)
     e = hipMemcpyAsync(d_init + 4 * spot0, h_init + 4 * spot0, sizeof(float) * 4 * nsp,
                        hipMemcpyHostToDevice, st);
-  int rc = SPOTFIT_OK;
-  if (e == hipSuccess)
+  if (e == hipSuccess && rc == SPOTFIT_OK)
     rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0, d_init + 4 * spot0,
                            nsp, &opt, d_params + 6 * spot0, d_chi2 + spot0, d_iters + spot0,
                            d_status + spot0, nullptr, st);
@@ -395,7 +403,7 @@ int spotfit_serve_create(spotfit_serve_t** out, int device, const spotfit_option
 int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_t arrival_ns,
                          uint64_t* ticket) {
   if (!sv || !fr || !ticket) return serve_fail(SPOTFIT_E_NULL, "serve_submit: NULL argument");
-  if (fr->n_spots < 0 || (fr->n_spots > 0 && (!fr->data || !fr->sizes || !fr->init || !fr->params_out ||
+  if (fr->n_spots < 0 || (fr->n_spots > 0 && (!fr->data || !fr->sizes || !fr->params_out ||
                                                !fr->chi2_out)))
     return serve_fail(SPOTFIT_E_ARG, "serve_submit: bad frame");
   if (fr->dtype != SPOTFIT_U16 && fr->dtype != SPOTFIT_F32) return serve_fail(SPOTFIT_E_ARG, "serve_submit: dtype");
@@ -423,6 +431,7 @@ int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_
   f = FrameRec();
   f.ticket = t;
   f.dtype = fr->dtype;
+  f.dev_init = fr->init == nullptr;
   f.n = n;
   f.spot0 = sv->spot_head;
   f.pix_off = sv->pix_head;
@@ -441,7 +450,7 @@ int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_
   // stage the frame (pinned mirrors); element offsets into the pixel ring
   std::memcpy(sv->h_pix + f.pix_off, fr->data, (size_t)(npx * esz));
   std::memcpy(sv->h_sizes + f.spot0, fr->sizes, sizeof(spotfit_shape_t) * n);
-  std::memcpy(sv->h_init + 4 * f.spot0, fr->init, sizeof(float) * 4 * n);
+  if (fr->init) std::memcpy(sv->h_init + 4 * f.spot0, fr->init, sizeof(float) * 4 * n);
   int64_t o = f.pix_off / esz;
   for (int64_t i = 0; i < n; ++i) {
     sv->h_offs[f.spot0 + i] = o;

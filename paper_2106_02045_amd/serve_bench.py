@@ -36,6 +36,8 @@ def main(argv=None):
     ap.add_argument("--schedule", default="mixed", choices=["mixed", "uniform"])
     ap.add_argument("--check", type=int, default=200, help="frames compared with a direct fit")
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--device-init", action="store_true",
+                    help="frames carry no start values: the loop computes them on the device")
     a = ap.parse_args(argv)
 
     import torch
@@ -52,7 +54,7 @@ def main(argv=None):
                     n_streams=a.streams)
     offs = np.round((arrivals - arrivals[0]) * 1e9).astype(np.uint64)
     w0 = time.perf_counter()
-    outs = srv.replay([(f.data, f.sizes, f.init) for f in frames], offs)
+    outs = srv.replay([(f.data, f.sizes, None if a.device_init else f.init) for f in frames], offs)
     wall = time.perf_counter() - w0
     st = srv.stats()
     srv.close()
@@ -66,7 +68,9 @@ def main(argv=None):
     for f in check:
         b = frames[f]
         up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-        g = ctx.fit_spots(up(b.data), up(b.sizes), up(b.offsets), up(b.init), opts)
+        init = (ctx.moment_init(up(b.data), up(b.sizes), up(b.offsets), opts) if a.device_init
+                else up(b.init))
+        g = ctx.fit_spots(up(b.data), up(b.sizes), up(b.offsets), init, opts)
         torch.cuda.synchronize()
         same = (np.array_equal(g["params"].cpu().numpy(), outs[f]["params"]) and
                 np.array_equal(g["status"].cpu().numpy(), outs[f]["status"]) and
@@ -95,6 +99,7 @@ def main(argv=None):
         "streams": a.streams,
         "budget_mb": a.budget_mb,
         "schedule": a.schedule,
+        "start_values": "device" if a.device_init else "host",
         "alone_vs_mix": {"frames_checked": int(len(check)), "frames_differing": mismatched},
         "data": "synthetic",
         "config": {"workload": "serve_fiducials", "frames": a.frames, "fps": a.fps,

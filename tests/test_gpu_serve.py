@@ -104,3 +104,28 @@ def test_serving_admission_by_memory(sf):
     ctx = sf.Context(0)
     alone = _fit(sf, ctx, frames[11], opts)
     np.testing.assert_array_equal(alone["params"], results[11]["params"])
+
+
+def test_serving_with_device_start_values(sf):
+    # frames without start values: the loop computes them on the device; the
+    # results equal a direct moment_init + fit of the same spots, bit for bit
+    import torch
+    ts, frames = spotgen.serve_frames(120, fps=5000.0, seed=11, threads=8)
+    opts = sf.default_options(max_side=21, schedule=sf.SCHEDULE_MIXED)
+    srv = sf.Server(0, opts, device_mem_budget=64 << 20, max_frames=256, n_streams=2)
+    offs = np.round((ts - ts[0]) * 1e9).astype(np.uint64)
+    outs = srv.replay([(f.data, f.sizes, None) for f in frames], offs)
+    st = srv.stats()
+    srv.close()
+    assert st["frames_done"] == len(frames) and st["frames_failed"] == 0
+    ctx = sf.Context(0)
+    dev = torch.device("cuda:0")
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    for f in range(0, len(frames), 17):
+        b = frames[f]
+        d = (up(b.data), up(b.sizes), up(b.offsets))
+        init = ctx.moment_init(*d, opts)
+        g = ctx.fit_spots(*d, init, opts)
+        torch.cuda.synchronize()
+        for k in ("params", "chi2", "iters", "status"):
+            np.testing.assert_array_equal(g[k].cpu().numpy(), outs[f][k])
