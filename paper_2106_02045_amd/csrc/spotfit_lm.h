@@ -81,5 +81,45 @@ __device__ __forceinline__ int tri_j(int t) {
   return t < 4 ? t : t < 7 ? t - 3 : t < 9 ? t - 5 : 3;
 }
 
+// a * b + c with c taken from a scalar register pair: keeps polynomial
+// constants out of vector registers (and out of the per-step copies a
+// vector-register accumulator would need).
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
+// e^x for x <= 0 (the argument of a Gaussian factor), within ~1 ulp:
+// x = n ln2 + r with |r| <= ln2 / 2 (Cody-Waite reduction with ln 2 split into
+// its double value and the double nearest the remainder, each step one fused
+// multiply-add), e^r by its Taylor series to degree 13 (truncation below 5e-18
+// relative on that interval), scaled by 2^n.  Underflows to 0 for x below
+// about -745; NaN stays NaN.
+__device__ __forceinline__ double exp_neg(double x) {
+  constexpr double kLog2e = 1.4426950408889634;
+  constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;   // ln 2 rounded to double
+  constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;  // ln 2 - kLn2Hi
+  const double n = __builtin_rint(x * kLog2e);
+  double r = __builtin_fma(-n, kLn2Hi, x);
+  r = __builtin_fma(-n, kLn2Lo, r);
+  // Taylor coefficients 1/k!, k = 13 .. 2, in Horner order
+  double p = 1.0 / 6227020800.0;                 // 1/13!
+  p = fma_s(p, r, 1.0 / 479001600.0);            // 1/12!
+  p = fma_s(p, r, 1.0 / 39916800.0);             // 1/11!
+  p = fma_s(p, r, 1.0 / 3628800.0);              // 1/10!
+  p = fma_s(p, r, 1.0 / 362880.0);               // 1/9!
+  p = fma_s(p, r, 1.0 / 40320.0);                // 1/8!
+  p = fma_s(p, r, 1.0 / 5040.0);                 // 1/7!
+  p = fma_s(p, r, 1.0 / 720.0);                  // 1/6!
+  p = fma_s(p, r, 1.0 / 120.0);                  // 1/5!
+  p = fma_s(p, r, 1.0 / 24.0);                   // 1/4!
+  p = fma_s(p, r, 1.0 / 6.0);                    // 1/3!
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)n);
+}
+
 }  // namespace lm
 }  // namespace sf

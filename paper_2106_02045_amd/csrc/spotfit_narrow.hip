@@ -255,8 +255,8 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
         for (int j = 0; j < CPL; ++j) {
           const int c = li + L * j;
           const double dxc = double(c) - x, dyr = double(c) - y;
-          ex[j] = c < w ? exp(dxc * dxc * hx) : 0.0;
-          eyl[j] = c < h ? exp(dyr * dyr * hy) : 0.0;
+          ex[j] = c < w ? exp_neg(dxc * dxc * hx) : 0.0;
+          eyl[j] = c < h ? exp_neg(dyr * dyr * hy) : 0.0;
           sxp += ex[j];
           sxxp = __builtin_fma(ex[j], ex[j], sxxp);
           syp += eyl[j];
