@@ -46,7 +46,10 @@
  *
  * Asynchrony: work is enqueued on the stream and the call returns; results
  * are valid after the stream is synchronised.  Calls on one context are not
- * thread-safe against each other.
+ * thread-safe against each other, and must not overlap on the device: the
+ * double-precision kernel hands spots out through a counter the context owns
+ * (and the mixed schedule through its workspace), so concurrent streams each
+ * need their own context (as the serving loop keeps one per stream).
  */
 #ifndef SPOTFIT_H
 #define SPOTFIT_H

@@ -29,6 +29,7 @@ struct spotfit_ctx {
   int32_t* ws;      // counters[8] then 3 lists of ws_cap spot indices
   int64_t ws_cap;
   unsigned long long* stats;  // device histogram buffer of spotfit_get_stats
+  int32_t* queue;             // spot counter of the narrow kernel's uniform launches
 };
 
 namespace {
@@ -200,10 +201,13 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
   c->ws = nullptr;
   c->ws_cap = 0;
   c->stats = nullptr;
+  c->queue = nullptr;
   e = hipMalloc((void**)&c->stats, sizeof(unsigned long long) * kStatsLen);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->queue, 256);
   if (e != hipSuccess) {
+    if (c->stats) (void)hipFree(c->stats);
     delete c;
-    return fail_hip(e, "hipMalloc (statistics buffer)");
+    return fail_hip(e, "hipMalloc (context buffers)");
   }
   // default plan per size class (measured on MI355X), all narrow: <= 8 px side:
   // 4 lanes x 2 columns; <= 16: 4 lanes x 4 columns; <= 32: 16 lanes x 2 columns
@@ -236,12 +240,13 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
 
 void spotfit_ctx_destroy(spotfit_ctx_t* ctx) {
   if (!ctx) return;
-  if (ctx->ws || ctx->stats) {
+  if (ctx->ws || ctx->stats || ctx->queue) {
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(ctx->device);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->stats) (void)hipFree(ctx->stats);
+    if (ctx->queue) (void)hipFree(ctx->queue);
     if (cur >= 0) (void)hipSetDevice(cur);
   }
   delete ctx;
@@ -313,6 +318,7 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   ka.iters_out = iters_out;
   ka.status_out = status_out;
   ka.evals_out = evals_out;
+  ka.queue = ctx->queue;
   ka.n = n;
   ka.dtype = dtype;
   ka.opt.max_iter = o.max_iter;
@@ -348,7 +354,22 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
     // persistent grid: as many one-wave workgroups as can be resident at once
     const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_plan[plan];
     const int grid = (int)(need < resident ? need : resident);
-    e = sf::launch_group_kernel(plan, ka, grid, (hipStream_t)stream);
+    // the narrow kernel's spot counter is 32-bit: batches of up to 2^30 spots per launch
+    const int64_t chunk = (int64_t)1 << 30;
+    e = hipSuccess;
+    for (int64_t c0 = 0; c0 < n && e == hipSuccess; c0 += chunk) {
+      sf::KArgs kc = ka;
+      kc.n = n - c0 < chunk ? n - c0 : chunk;
+      kc.sizes = sizes + c0;
+      kc.offsets = offsets + c0;
+      kc.init = init + 4 * c0;
+      kc.params_out = params_out + 6 * c0;
+      kc.chi2_out = chi2_out + c0;
+      kc.iters_out = iters_out + c0;
+      kc.status_out = status_out + c0;
+      kc.evals_out = evals_out ? evals_out + 2 * c0 : nullptr;
+      e = sf::launch_group_kernel(plan, kc, grid, (hipStream_t)stream);
+    }
   } else if (o.precision == SPOTFIT_PREC_FP32_PLAIN) {
     const int threads = ((o.max_pixels + 63) / 64) * 64;
     e = sf::launch_plain_kernel(ka, threads, (hipStream_t)stream);

@@ -35,6 +35,7 @@ struct KArgs {
   int32_t* iters_out;
   int32_t* status_out;
   int32_t* evals_out;
+  int32_t* queue;  // spot counter of the narrow kernel's uniform launch (context-owned)
   int64_t n;
   int dtype;
   int pad_;
@@ -75,6 +76,7 @@ int wide_plan_count();
 int narrow_plan_count();
 void narrow_plan_shape(int plan, int* lanes, int* cpl);
 const void* narrow_kernel_symbol(int plan);
+// Resets ka.queue, then fits ka.n < 2^31 spots handed out through that counter.
 hipError_t launch_narrow_kernel(int plan, const KArgs& ka, int grid, hipStream_t st);
 int narrow_mixed_plan_count();
 const void* narrow_mixed_kernel_symbol(int plan);

@@ -60,33 +60,15 @@ __device__ __forceinline__ void gather_rows(const double (&own)[CPL], double (&a
 // (which also holds up every later LDS wait).
 __device__ float kZeros[32 * 32];
 
-// Spots s = base + group, then + stride, ... of a uniform batch.
-struct StridedSrc {
-  int64_t n, base, stride;
-  __device__ int64_t first(int gi, int) const {
-    const int64_t s = base + gi;
-    return s < n ? s : -1;
-  }
-  __device__ int64_t next(int64_t s, int) const {
-    s += stride;
-    return s < n ? s : -1;
-  }
-};
-
-// Spots of one size class, taken from its list through an atomic counter.
-template <int L>
-struct QueueSrc {
+// The spots a launch fits: queue position i (0 <= i < count) is spot list[i],
+// or spot i itself when list is null.  Wavefronts reserve positions from the
+// shared counter a chunk at a time and hand them to their groups one by one as
+// the groups finish spots, so every group stays busy until the queue is empty
+// (a fixed share per group leaves the fastest groups idle at the end).
+struct SpotQueue {
   const int32_t* list;
   int32_t* take;
   int32_t count;
-  __device__ int64_t pull(int li) const {
-    int v = 0;
-    if (li == 0) v = atomicAdd(take, 1);
-    v = gbcast_i<L, 0>(v);
-    return v < count ? (int64_t)list[v] : -1;
-  }
-  __device__ int64_t first(int, int li) const { return pull(li); }
-  __device__ int64_t next(int64_t, int li) const { return pull(li); }
 };
 
 // Per-group state kept in LDS between the steps of an iteration.
@@ -111,8 +93,8 @@ __device__ __forceinline__ double pixel(uint32_t v) {
 // Fit every spot the source hands to this wavefront's groups.
 // L lanes per spot, CPL columns per lane: spots with w, h <= L * CPL; pixel
 // data type DT (SPOTFIT_U16 or SPOTFIT_F32).
-template <int L, int CPL, int DT, class Src>
-__device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NState* sts) {
+template <int L, int CPL, int DT>
+__device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, NState* sts) {
   constexpr int HM = L * CPL;
   const int lane = __lane_id();
   const int gi = lane / L;
@@ -122,6 +104,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
 
   int64_t s = -1;  // the group's current spot
   int w = 0, h = 0, k = 0, it = 0, status = 0, mode = kNew, n_grad = 0, n_trial = 0;
+  bool bad = false;  // the current spot is unusable: it ends at its first step as BAD_INPUT
   bool sym = true, small = false;
 
   // pixels of the lane's columns as loaded (0 outside the spot); converted where
@@ -138,71 +121,88 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
   // ever reads back its own writes: no synchronisation is needed.
   NState& S = sts[gi];
 
-  // The next spot's description is loaded one spot ahead, so that a fetch can
-  // issue the pixel loads at once; nothing in the fetch uses a loaded pixel, so
-  // the loads complete behind the rest of the wave step.
-  int64_t ns = src.first(gi, li);
+  // Each group holds a reserved next spot whose description (shape, offset,
+  // start values) is loaded one spot ahead, so that taking a spot never waits.
+  int64_t ns = -1;
   spotfit_shape_t nsh{0, 0, 0, 0};
   int64_t noff = 0;
   float4 nin = make_float4(0.f, 0.f, 0.f, 0.f);
-  auto prefetch = [&]() {
-    if (ns >= 0) {
-      nsh = ka.sizes[ns];
-      noff = ka.offsets[ns];
-      const float* in = ka.init + 4 * ns;
-      nin = make_float4(in[0], in[1], in[2], in[3]);
+
+  // Queue positions: the wavefront's current chunk [cbase, cbase + kChunk) of
+  // which cused are handed out, and the next chunk, reserved one chunk ahead
+  // (its base arrives in lane 0 long before it is needed).
+  constexpr int kChunk = 2 * (64 / L);
+  int cbase = 0, cused = 0, nbase_l0 = 0;
+  {
+    int b0 = 0, b1 = 0;
+    if (lane == 0) {
+      b0 = atomicAdd(q.take, kChunk);
+      b1 = atomicAdd(q.take, kChunk);
+    }
+    cbase = __builtin_amdgcn_readfirstlane(b0);
+    nbase_l0 = b1;
+  }
+  // Give every group with `want` a new reserved spot.  Called with the whole
+  // wavefront active (the chunk state is wavefront-uniform).
+  auto reserve = [&](bool want) {
+    const bool req = want && li == 0;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(req);
+    const int nreq = __builtin_popcountll(m);
+    if (nreq == 0) return;
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    int pos;
+    if (cused + nreq > kChunk) {
+      const int nb = __builtin_amdgcn_readfirstlane(nbase_l0);
+      pos = cused + rank < kChunk ? cbase + cused + rank : nb + (cused + rank - kChunk);
+      cbase = nb;
+      cused = cused + nreq - kChunk;
+      if (lane == 0) nbase_l0 = atomicAdd(q.take, kChunk);
+    } else {
+      pos = cbase + cused + rank;
+      cused += nreq;
+    }
+    const int p = gbcast_i<L, 0>(req ? pos : 0);
+    if (want) {
+      ns = (uint32_t)p < (uint32_t)q.count ? (q.list ? (int64_t)q.list[p] : (int64_t)p) : -1;
+      if (ns >= 0) {
+        nsh = ka.sizes[ns];
+        noff = ka.offsets[ns];
+        const float* in = ka.init + 4 * ns;
+        nin = make_float4(in[0], in[1], in[2], in[3]);
+      }
     }
   };
-  prefetch();
 
-  // Take the next spot of this group (its description only), writing
-  // BAD_INPUT for unusable ones.
+  // Take the reserved spot (its description only); an unusable one is marked
+  // and ends at its next step with BAD_INPUT.
   int64_t off = 0;  // element offset of the current spot's pixels
   auto advance = [&]() {
-    while (ns >= 0) {
-      s = ns;
-      const spotfit_shape_t sh = nsh;
-      const float i0 = nin.x, i1 = nin.y, i2 = nin.z, i3 = nin.w;
-      off = noff;
-      ns = src.next(s, li);
-      prefetch();
-      const int mdl = sh.model;
-      const bool ell = mdl == SPOTFIT_ELL;
-      const bool bad = sh.w < 3 || sh.h < 3 || sh.w > HM || sh.h > HM ||
-                       sh.w * sh.h > o.max_pixels || sh.w > o.max_side || sh.h > o.max_side ||
-                       (mdl != SPOTFIT_SYM && !ell) || !__builtin_isfinite(i0) ||
-                       !__builtin_isfinite(i1) || !__builtin_isfinite(i2) || !(i2 > 0.f) ||
-                       (ell && (!__builtin_isfinite(i3) || !(i3 > 0.f)));
-      if (!bad) {
-        w = sh.w;
-        h = sh.h;
-        sym = !ell;
-        pc[0] = i0;
-        pc[1] = i1;
-        pc[2] = i2;
-        pc[3] = ell ? (double)i3 : (double)i2;
-        Tme = o.max_error_per_px * double(w * h);
-        k = o.lambda0_exp10;
-        it = 0;
-        status = SPOTFIT_MAX_ITER;
-        mode = kNew;
-        n_grad = n_trial = 0;
-        return;
-      }
-      if (li == 0) {
-        const float nanf = __builtin_nanf("");
-#pragma unroll
-        for (int q = 0; q < 6; ++q) ka.params_out[6 * s + q] = nanf;
-        ka.chi2_out[s] = nanf;
-        ka.iters_out[s] = 0;
-        ka.status_out[s] = SPOTFIT_BAD_INPUT;
-        if (ka.evals_out) {
-          ka.evals_out[2 * s] = 0;
-          ka.evals_out[2 * s + 1] = 0;
-        }
-      }
-    }
-    s = -1;
+    s = ns;
+    ns = -1;
+    if (s < 0) return;
+    const spotfit_shape_t sh = nsh;
+    const float i0 = nin.x, i1 = nin.y, i2 = nin.z, i3 = nin.w;
+    off = noff;
+    const int mdl = sh.model;
+    const bool ell = mdl == SPOTFIT_ELL;
+    bad = sh.w < 3 || sh.h < 3 || sh.w > HM || sh.h > HM || sh.w * sh.h > o.max_pixels ||
+          sh.w > o.max_side || sh.h > o.max_side || (mdl != SPOTFIT_SYM && !ell) ||
+          !__builtin_isfinite(i0) || !__builtin_isfinite(i1) || !__builtin_isfinite(i2) ||
+          !(i2 > 0.f) || (ell && (!__builtin_isfinite(i3) || !(i3 > 0.f)));
+    w = bad ? 0 : sh.w;
+    h = bad ? 0 : sh.h;
+    sym = !ell;
+    pc[0] = i0;
+    pc[1] = i1;
+    pc[2] = i2;
+    pc[3] = ell ? (double)i3 : (double)i2;
+    Tme = o.max_error_per_px * double(w * h);
+    k = o.lambda0_exp10;
+    it = 0;
+    status = SPOTFIT_MAX_ITER;
+    mode = kNew;
+    n_grad = n_trial = 0;
   };
 
   // The current spot's pixels into g, every slot at once and with no predicated
@@ -240,11 +240,29 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
     }
   };
 
+  reserve(true);
   advance();
+  reserve(true);
   load_pixels();
 
   while (__builtin_amdgcn_ballot_w64(s >= 0) != 0) {
-    if (s >= 0) {
+    bool took = false;
+    if (s >= 0 && bad) {
+      if (li == 0) {
+        const float nanf = __builtin_nanf("");
+#pragma unroll
+        for (int q2 = 0; q2 < 6; ++q2) ka.params_out[6 * s + q2] = nanf;
+        ka.chi2_out[s] = nanf;
+        ka.iters_out[s] = 0;
+        ka.status_out[s] = SPOTFIT_BAD_INPUT;
+        if (ka.evals_out) {
+          ka.evals_out[2 * s] = 0;
+          ka.evals_out[2 * s + 1] = 0;
+        }
+      }
+      advance();
+      took = true;
+    } else if (s >= 0) {
       // ================= trial evaluation at pc (Eqs. 2, 5, 6, 10) =================
       {
         const double x = pc[0], y = pc[1];
@@ -434,6 +452,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
           }
         }
         advance();
+        took = true;
       }
 
       // ================= derivative pass at pc (Eqs. 7-9, 11) =================
@@ -538,19 +557,17 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const Src& src, NSta
                 (sym || fabs(d[3]) < o.min_step_rel * fabs(b3));
       }
 
-      // pixels for the next step's evaluation (the next spot's after a fetch)
-      load_pixels();
-
     }
+    // pixels for the next step's evaluation (the next spot's after a take)
+    if (s >= 0) load_pixels();
+    reserve(took);
   }
 }
 
 template <int L, int CPL, int WPE, int DT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_narrow_kernel(KArgs ka) {
-  constexpr int G = 64 / L;
-  __shared__ NState sts[G];
-  const StridedSrc src{ka.n, (int64_t)blockIdx.x * G, (int64_t)gridDim.x * G};
-  fit_narrow<L, CPL, DT>(ka, src, sts);
+  __shared__ NState sts[64 / L];
+  fit_narrow<L, CPL, DT>(ka, SpotQueue{nullptr, ka.queue, (int32_t)ka.n}, sts);
 }
 
 // Batches of uneven spot sizes: the classify pass of the wide kernel's mixed
@@ -568,11 +585,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     int32_t* take = ws.counters + 3 + c;
     const int32_t count = ws.counters[c];
     if (c == 0)
-      fit_narrow<L0, C0, DT>(ka, QueueSrc<L0>{list, take, count}, sts);
+      fit_narrow<L0, C0, DT>(ka, SpotQueue{list, take, count}, sts);
     else if (c == 1)
-      fit_narrow<L1, C1, DT>(ka, QueueSrc<L1>{list, take, count}, sts);
+      fit_narrow<L1, C1, DT>(ka, SpotQueue{list, take, count}, sts);
     else
-      fit_narrow<L2, C2, DT>(ka, QueueSrc<L2>{list, take, count}, sts);
+      fit_narrow<L2, C2, DT>(ka, SpotQueue{list, take, count}, sts);
   }
 }
 
@@ -640,7 +657,14 @@ hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws,
   return hipErrorInvalidValue;
 }
 
+__global__ void queue_reset_kernel(int32_t* take) {
+  if (threadIdx.x == 0) *take = 0;
+}
+
 hipError_t launch_narrow_kernel(int plan, const KArgs& ka, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, ka.queue);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
 #define SF_NLAUNCH(I, L, C, W)                                                                \
   if (plan == I) {                                                                            \
     if (ka.dtype == SPOTFIT_U16)                                                              \
