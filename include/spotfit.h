@@ -103,6 +103,17 @@ typedef enum {
                                    spotfit_ctx_reserve)                                 */
 } spotfit_schedule_t;
 
+/* Which lane mapping the double-precision kernel uses. */
+typedef enum {
+  SPOTFIT_PLAN_THROUGHPUT = 0, /* default: few lanes per spot (4 up to 16x16), the most spots
+                                  per second for batches that fill the GPU              */
+  SPOTFIT_PLAN_LATENCY = 1     /* one lane per column (8, 16 or 32 lanes per spot): each
+                                  evaluation step is shorter, so a batch too small to
+                                  fill the GPU (a camera frame) finishes sooner; results
+                                  agree with the other plan in every decision but may
+                                  differ in the last bits                               */
+} spotfit_plan_hint_t;
+
 typedef enum {
   SPOTFIT_OK = 0,
   SPOTFIT_E_NULL = -1,     /* NULL context, output or input array with n > 0           */
@@ -137,7 +148,7 @@ typedef struct {
   int32_t max_side;         /* capacity promise: spots with w or h > max_side are
                                BAD_INPUT; smaller values select narrower lane groups (32) */
   int32_t schedule;         /* SPOTFIT_PREC_FP64 only: spotfit_schedule_t (UNIFORM)        */
-  int32_t reserved;         /* 0                                                           */
+  int32_t plan_hint;        /* SPOTFIT_PREC_FP64 only: spotfit_plan_hint_t (THROUGHPUT)      */
 } spotfit_options_t;
 
 /* Fill *opt with the paper's settings (Results section) and the defaults above. */

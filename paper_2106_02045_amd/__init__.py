@@ -20,6 +20,7 @@ MAX_ITER, MAX_ERROR, MIN_DELTA, MIN_STEP, NOT_CONVERGED, BAD_INPUT = range(6)
 STATUS_NAMES = ["MAX_ITER", "MAX_ERROR", "MIN_DELTA", "MIN_STEP", "NOT_CONVERGED", "BAD_INPUT"]
 PREC_FP32, PREC_MIXED, PREC_FP64, PREC_FP32_PLAIN = 0, 1, 2, 3
 SCHEDULE_UNIFORM, SCHEDULE_MIXED = 0, 1
+PLAN_THROUGHPUT, PLAN_LATENCY = 0, 1
 
 EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_create",
             "spotfit_ctx_destroy", "spotfit_ctx_reserve", "spotfit_fit_spots",
@@ -51,7 +52,7 @@ class Options(ctypes.Structure):
         ("max_pixels", ctypes.c_int32),
         ("max_side", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("plan_hint", ctypes.c_int32),
     ]
 
 
@@ -172,7 +173,7 @@ def default_options(**kw) -> Options:
     o = Options()
     lib().spotfit_default_options(ctypes.byref(o))
     for k, v in kw.items():
-        if not hasattr(o, k) or k == "reserved":
+        if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
     return o

@@ -112,6 +112,7 @@ void spotfit_default_options(spotfit_options_t* o) {
   o->max_pixels = 1024;           // Implementation section: at most 1024 pixels per fit
   o->max_side = 32;
   o->schedule = SPOTFIT_SCHEDULE_UNIFORM;
+  o->plan_hint = SPOTFIT_PLAN_THROUGHPUT;
 }
 
 int spotfit_validate_options(const spotfit_options_t* o) {
@@ -141,6 +142,8 @@ int spotfit_validate_options(const spotfit_options_t* o) {
     return fail(SPOTFIT_E_OPTIONS, "max_side not in [3, 32]");
   if (o->schedule != SPOTFIT_SCHEDULE_UNIFORM && o->schedule != SPOTFIT_SCHEDULE_MIXED)
     return fail(SPOTFIT_E_OPTIONS, "unknown schedule");
+  if (o->plan_hint != SPOTFIT_PLAN_THROUGHPUT && o->plan_hint != SPOTFIT_PLAN_LATENCY)
+    return fail(SPOTFIT_E_OPTIONS, "unknown plan hint");
   return SPOTFIT_OK;
 }
 
@@ -340,13 +343,17 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
       if (rr != SPOTFIT_OK) return rr;
     }
     sf::MixedWs ws{ctx->ws, ctx->ws + 8, ctx->ws_cap};
-    const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_mixed[ctx->mixed_plan];
+    // latency: the wide mixed-size plan (8, 16, 32 lanes per spot)
+    const int mplan = o.plan_hint == SPOTFIT_PLAN_LATENCY ? 0 : ctx->mixed_plan;
+    const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_mixed[mplan];
     const int64_t need = (n + 1) / 2;
     const int grid = (int)(need < resident ? need : resident);
-    e = sf::launch_mixed(ctx->mixed_plan, ka, ws, grid, (hipStream_t)stream);
+    e = sf::launch_mixed(mplan, ka, ws, grid, (hipStream_t)stream);
   } else if (o.precision == SPOTFIT_PREC_FP64) {
     const int cls = o.max_side <= 8 ? 0 : o.max_side <= 16 ? 1 : 2;
-    const int plan = ctx->plan_for_class[cls];
+    // latency: the wide plans with one lane per column (8x1, 16x1, 32x1)
+    const int wide_for_class[3] = {0, 2, 4};
+    const int plan = o.plan_hint == SPOTFIT_PLAN_LATENCY ? wide_for_class[cls] : ctx->plan_for_class[cls];
     int lanes = 0, cpl = 0;
     sf::group_plan_shape(plan, &lanes, &cpl);
     const int64_t per_wave = 64 / lanes;

@@ -129,18 +129,17 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
   float4 nin = make_float4(0.f, 0.f, 0.f, 0.f);
 
   // Queue positions: the wavefront's current chunk [cbase, cbase + kChunk) of
-  // which cused are handed out, and the next chunk, reserved one chunk ahead
-  // (its base arrives in lane 0 long before it is needed).
-  constexpr int kChunk = 2 * (64 / L);
+  // which cused are handed out, and the next chunk, requested from the counter
+  // once half of the current one is out (its base, in lane 0, is normally back
+  // before it is needed).  A chunk is one position per group, so that a small
+  // batch spreads over many wavefronts instead of queueing on a few.
+  constexpr int kChunk = 64 / L;
   int cbase = 0, cused = 0, nbase_l0 = 0;
+  bool nb_asked = false;
   {
-    int b0 = 0, b1 = 0;
-    if (lane == 0) {
-      b0 = atomicAdd(q.take, kChunk);
-      b1 = atomicAdd(q.take, kChunk);
-    }
+    int b0 = 0;
+    if (lane == 0) b0 = atomicAdd(q.take, kChunk);
     cbase = __builtin_amdgcn_readfirstlane(b0);
-    nbase_l0 = b1;
   }
   // Give every group with `want` a new reserved spot.  Called with the whole
   // wavefront active (the chunk state is wavefront-uniform).
@@ -152,15 +151,20 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     int pos;
-    if (cused + nreq > kChunk) {
+    if (cused + nreq > kChunk) {  // nreq <= kChunk: the rest comes from the next chunk
+      if (!nb_asked && lane == 0) nbase_l0 = atomicAdd(q.take, kChunk);
       const int nb = __builtin_amdgcn_readfirstlane(nbase_l0);
       pos = cused + rank < kChunk ? cbase + cused + rank : nb + (cused + rank - kChunk);
       cbase = nb;
       cused = cused + nreq - kChunk;
-      if (lane == 0) nbase_l0 = atomicAdd(q.take, kChunk);
+      nb_asked = false;
     } else {
       pos = cbase + cused + rank;
       cused += nreq;
+    }
+    if (!nb_asked && 2 * cused >= kChunk) {
+      if (lane == 0) nbase_l0 = atomicAdd(q.take, kChunk);
+      nb_asked = true;
     }
     const int p = gbcast_i<L, 0>(req ? pos : 0);
     if (want) {
@@ -597,7 +601,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 
 // The compiled narrow plans: (lanes per spot, columns per lane, min waves per SIMD).
 #define SF_NARROW_PLANS(X) \
-  X(0, 4, 2, 3)            \
+  X(0, 4, 2, 2)            \
   X(1, 4, 4, 2)            \
   X(2, 8, 2, 2)            \
   X(3, 16, 2, 2)

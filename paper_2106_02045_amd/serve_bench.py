@@ -36,6 +36,8 @@ def main(argv=None):
     ap.add_argument("--schedule", default="mixed", choices=["mixed", "uniform"])
     ap.add_argument("--check", type=int, default=200, help="frames compared with a direct fit")
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--plan", default="latency", choices=["latency", "throughput"],
+                    help="lane mapping of the fit (latency: one lane per column)")
     ap.add_argument("--device-init", action="store_true",
                     help="frames carry no start values: the loop computes them on the device")
     a = ap.parse_args(argv)
@@ -49,7 +51,8 @@ def main(argv=None):
     arrivals, frames = spotgen.serve_frames(a.frames, fps=a.fps, seed=a.seed, threads=16)
     gen_s = time.time() - t0
     opts = sf.default_options(max_side=21, schedule=(sf.SCHEDULE_MIXED if a.schedule == "mixed"
-                                                     else sf.SCHEDULE_UNIFORM))
+                                                     else sf.SCHEDULE_UNIFORM),
+                              plan_hint=(sf.PLAN_LATENCY if a.plan == "latency" else sf.PLAN_THROUGHPUT))
     srv = sf.Server(0, opts, device_mem_budget=a.budget_mb << 20, max_frames=a.max_frames,
                     n_streams=a.streams)
     offs = np.round((arrivals - arrivals[0]) * 1e9).astype(np.uint64)
@@ -100,6 +103,7 @@ def main(argv=None):
         "budget_mb": a.budget_mb,
         "schedule": a.schedule,
         "start_values": "device" if a.device_init else "host",
+        "plan": a.plan,
         "alone_vs_mix": {"frames_checked": int(len(check)), "frames_differing": mismatched},
         "data": "synthetic",
         "config": {"workload": "serve_fiducials", "frames": a.frames, "fps": a.fps,

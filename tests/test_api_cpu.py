@@ -69,7 +69,7 @@ def test_default_options_are_the_papers():
     ("max_iter", -1), ("max_iter", 5000), ("precision", 7), ("min_delta", 1.0),
     ("min_delta", -1e-3), ("tie_tau", 1.5), ("sigma_min", 0.0), ("max_pixels", 2000),
     ("max_pixels", 4), ("max_error_per_px", float("nan")), ("sigma_max_frac", 0.05),
-    ("max_side", 2), ("max_side", 33), ("schedule", 2),
+    ("max_side", 2), ("max_side", 33), ("schedule", 2), ("plan_hint", 2), ("plan_hint", -1),
 ])
 def test_bad_options_rejected(field, value):
     o = sf.default_options()

@@ -129,3 +129,22 @@ def test_serving_with_device_start_values(sf):
         torch.cuda.synchronize()
         for k in ("params", "chi2", "iters", "status"):
             np.testing.assert_array_equal(g[k].cpu().numpy(), outs[f][k])
+
+
+def test_latency_plan_in_serving_matches_direct_calls(sf):
+    # the latency hint (one lane per column) in the serving loop and in direct calls:
+    # identical bits, and the oracle's decisions
+    ts, frames = spotgen.serve_frames(80, fps=5000.0, seed=12, threads=8)
+    opts = sf.default_options(max_side=21, schedule=sf.SCHEDULE_MIXED, plan_hint=sf.PLAN_LATENCY)
+    srv = sf.Server(0, opts, device_mem_budget=64 << 20, max_frames=256, n_streams=2)
+    offs = np.round((ts - ts[0]) * 1e9).astype(np.uint64)
+    outs = srv.replay([(f.data, f.sizes, f.init) for f in frames], offs)
+    srv.close()
+    ctx = sf.Context(0)
+    for f in range(0, len(frames), 13):
+        alone = _fit(sf, ctx, frames[f], opts)
+        for k in ("params", "chi2", "iters", "status"):
+            np.testing.assert_array_equal(alone[k], outs[f][k])
+    r = oracle.fit_batch(frames[0], oracle.default_opts(), threads=4)
+    c = compare(outs[0], r, chi_band=1e-11, step_band=1e-9)
+    assert c["strict_mismatch"] == 0 and c["tol_fail_same"] == 0
