@@ -33,17 +33,19 @@ C_GRAD = {0: 66, 1: 88}
 C_TRIAL = 16
 
 
+# the narrow fit kernel's source and the headers its code comes from
+FIT_KERNEL_SOURCES = ("spotfit_narrow.hip", "spotfit_internal.h", "spotfit_lm.h", "lanegroup.h",
+                      "xlane.h")
+
+
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources and headers the fit kernels are built from."""
+    """sha256 over the sources the fit kernel is built from."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2106_02045_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
-    with open(os.path.join(ROOT, "include", "spotfit.h"), "rb") as fh:
-        h.update(fh.read())
+    for name in FIT_KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 

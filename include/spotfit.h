@@ -198,6 +198,22 @@ int spotfit_moment_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                         const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n_spots,
                         const spotfit_options_t* opt, float* init_out, void* stream);
 
+/* The start values the paper uses for its accuracy runs (Results section):
+ * the image smoothed by a 3 x 3 moving average (each pixel: the mean of the
+ * window pixels that lie inside the ROI), the centre put on the smoothed
+ * pixel with the highest value (on ties the first in row-major order),
+ * beta0 = lowest raw pixel, alpha0 = highest raw pixel - beta0, and
+ * sigma = sqrt(M / pi) with M the number of raw pixels whose value exceeds
+ * alpha0 exp(-1/2) + beta0 (formed with one rounding, in double); sigma is at
+ * least 0.5 (a flat spot has M = 0).  init_out[s] = (x0, y0, sigma, sigma)
+ * for either model.  Window sums are taken in double and are exact for 16-bit
+ * pixels (and for float pixels within 2^26 of each other), so the brightest
+ * pixel does not depend on the order of additions.  Arguments, unusable
+ * shapes (NaN), ownership, stream and return codes as spotfit_moment_init. */
+int spotfit_peak_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                      const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n_spots,
+                      const spotfit_options_t* opt, float* init_out, void* stream);
+
 /* Stop reasons and iteration counts of a fitted batch: the statistics the
  * paper reports in its Number of iterations section (Fig. 8). */
 typedef struct {
@@ -250,6 +266,16 @@ int spotfit_autotune(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
 /* ------------------------------------------------------------------------ */
 typedef struct spotfit_serve spotfit_serve_t; /* opaque */
 
+/* Drift of the sample in one tracked frame (see spotfit_serve_track). */
+typedef struct {
+  float dx, dy;            /* mean of (x - ref_x, y - ref_y) over the counted markers
+                              (pixels; NaN when none counts)                          */
+  float mean_dx, mean_dy;  /* mean of (dx, dy) over the last `window` tracked frames
+                              that counted a marker, this one included (NaN if none)  */
+  int32_t n_used;          /* markers counted in this frame                           */
+  int32_t n_frames;        /* frames in the window mean                               */
+} spotfit_drift_t;
+
 /* One camera frame, all pointers HOST memory.  Spots lie back to back in `data`
  * (row-major each, no offsets array).  The input buffers may be reused as soon
  * as submit returns; the output arrays must stay valid until the frame is done. */
@@ -264,6 +290,8 @@ typedef struct {
   float* chi2_out;               /* n_spots                                            */
   int32_t* iters_out;            /* n_spots, or NULL                                   */
   int32_t* status_out;           /* n_spots, or NULL                                   */
+  spotfit_drift_t* drift_out;    /* NULL, or one record: the frame is a tracked frame
+                                    (spotfit_serve_track) and its drift lands here     */
 } spotfit_frame_t;
 
 typedef struct {
@@ -283,9 +311,28 @@ typedef struct {
 int spotfit_serve_create(spotfit_serve_t** sv, int device, const spotfit_options_t* opt,
                          size_t device_mem_budget, int32_t max_frames, int32_t n_streams);
 
+/* Drift tracking of fiducial markers inside the serving loop (the paper's use:
+ * marker positions averaged over markers and frames to stabilise the sample,
+ * Introduction).  After tracking is set, a frame submitted with drift_out !=
+ * NULL must hold exactly n_markers spots, spot k being marker k; right after
+ * its fit, on the device, a marker counts when its fit stopped on MAX_ERROR,
+ * MIN_DELTA or MIN_STEP with finite x and y, the frame's drift is the mean of
+ * (x - ref_x, y - ref_y) over the counted markers (in ROI pixel coordinates,
+ * summed in double), and the tracked drift is the mean of the frame drifts of
+ * the last `window` tracked frames that counted a marker (in submission order).
+ * ref_xy: HOST float[n_markers][2], copied.  n_markers in [1, 65536], window
+ * in [1, 65536]; n_markers = 0 turns tracking off.  Allocates device memory
+ * for the reference and history; restarts the sequence.  Call it with no frame
+ * in flight: otherwise SPOTFIT_E_AGAIN.  Returns SPOTFIT_OK or a negative
+ * spotfit_error_t. */
+int spotfit_serve_track(spotfit_serve_t* sv, int32_t n_markers, const float* ref_xy,
+                        int32_t window);
+
 /* Submit a frame; `arrival_ns` is its arrival time on the steady clock in ns
  * (0 = now), from which its latency is measured.  Returns SPOTFIT_OK and a
- * ticket, or SPOTFIT_E_AGAIN when memory or slots are short (nothing queued). */
+ * ticket, or SPOTFIT_E_AGAIN when memory or slots are short (nothing queued).
+ * A frame with drift_out but tracking off or a spot count other than the
+ * tracked marker count: SPOTFIT_E_ARG. */
 int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* frame, uint64_t arrival_ns,
                          uint64_t* ticket);
 

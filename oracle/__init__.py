@@ -6,6 +6,8 @@ the CPU-baseline leg of the benchmark may import this module; the product
 package never does.  It shares no code with the HIP path.
 
 Parity status: see the header of spotfit_oracle.h (what pins each function).
+drift_track (the drift-tracking consumer of fitted marker positions) is plain
+numpy here, pinned by exact shifts, excluded markers and a linear drift.
 """
 from __future__ import annotations
 
@@ -93,6 +95,10 @@ def lib():
         L.orc_moment_init.restype = ctypes.c_int
         L.orc_moment_init_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp]
         L.orc_moment_init_batch.restype = ctypes.c_int
+        L.orc_peak_init.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_peak_init.restype = ctypes.c_int
+        L.orc_peak_init_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp]
+        L.orc_peak_init_batch.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -202,4 +208,62 @@ def moment_init_batch(batch) -> np.ndarray:
     out = np.empty((batch.n, 4))
     lib().orc_moment_init_batch(data.ctypes.data, dtype, sizes.ctypes.data, offs.ctypes.data,
                                 int(batch.n), out.ctypes.data)
+    return out
+
+
+def peak_init(g, w: int, h: int) -> np.ndarray:
+    """The paper's start values of one spot (orc_peak_init)."""
+    g = np.ascontiguousarray(g, dtype=np.float64).ravel()
+    out = np.empty(4)
+    lib().orc_peak_init(_dp(g), int(w), int(h), _dp(out))
+    return out
+
+
+def peak_init_batch(batch) -> np.ndarray:
+    """orc_peak_init over a SpotBatch; float64 [n, 4]."""
+    data = np.ascontiguousarray(batch.data)
+    dtype = 0 if data.dtype == np.uint16 else 1
+    if dtype == 1 and data.dtype != np.float32:
+        raise TypeError("data must be uint16 or float32")
+    sizes = np.ascontiguousarray(batch.sizes, dtype=np.uint8)
+    offs = np.ascontiguousarray(batch.offsets, dtype=np.int64)
+    out = np.empty((batch.n, 4))
+    lib().orc_peak_init_batch(data.ctypes.data, dtype, sizes.ctypes.data, offs.ctypes.data,
+                              int(batch.n), out.ctypes.data)
+    return out
+
+
+def drift_track(params, status, ref_xy, window: int):
+    """Drift of fiducial markers over a sequence of frames (the paper's use of the
+    fit: tracking markers and averaging their positions over markers and frames to
+    stabilise the sample, Introduction).
+
+    params [F, M, 6] and status [F, M]: the fits of M markers in F frames, in
+    order; ref_xy [M, 2]: each marker's reference position.  A marker counts in a
+    frame when its fit stopped on MAX_ERROR, MIN_DELTA or MIN_STEP with finite x
+    and y.  Per frame: (dx, dy) = mean over the counted markers of
+    (x - ref_x, y - ref_y) (NaN when none counts); (Dx, Dy) = mean of (dx, dy)
+    over those of the last `window` frames (this one included) that had a
+    counted marker; n_used, n_frames = the two counts.  Returns float64 [F, 6]
+    = (dx, dy, Dx, Dy, n_used, n_frames).
+    """
+    p = np.asarray(params, dtype=np.float64)
+    st = np.asarray(status)
+    ref = np.asarray(ref_xy, dtype=np.float64)
+    F = p.shape[0]
+    out = np.full((F, 6), np.nan)
+    per = []
+    for f in range(F):
+        x, y = p[f, :, 0], p[f, :, 1]
+        ok = np.isin(st[f], (MAX_ERROR, MIN_DELTA, MIN_STEP)) & np.isfinite(x) & np.isfinite(y)
+        n = int(ok.sum())
+        dx = float(np.sum(x[ok] - ref[ok, 0]) / n) if n else np.nan
+        dy = float(np.sum(y[ok] - ref[ok, 1]) / n) if n else np.nan
+        per.append((dx, dy, n))
+        win = [e for e in per[max(0, f - window + 1):] if e[2] > 0]
+        out[f, 0], out[f, 1], out[f, 4] = dx, dy, n
+        if win:
+            out[f, 2] = sum(e[0] for e in win) / len(win)
+            out[f, 3] = sum(e[1] for e in win) / len(win)
+        out[f, 5] = len(win)
     return out

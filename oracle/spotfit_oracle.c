@@ -484,3 +484,71 @@ int orc_moment_init_batch(const void* data, int dtype, const uint8_t* sizes,
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's own start values for its accuracy runs (Results section,      */
+/* initial parameters): smooth the image with a 3 x 3 moving average (here   */
+/* the mean over the part of the window inside the ROI); the centre is the   */
+/* smoothed pixel with the highest value (the first one in row-major order   */
+/* on ties); beta0 = lowest raw pixel, alpha0 = highest raw pixel - beta0;   */
+/* sigma = sqrt(M / pi) with M the number of raw pixels whose value exceeds  */
+/* alpha0 exp(-1/2) + beta0 (that threshold formed with a single rounding);  */
+/* sigma is kept >= 0.5 (a flat image has M = 0).  Both sigmas get the same */
+/* value.                                                                    */
+/* ------------------------------------------------------------------------ */
+int orc_peak_init(const double* g, int w, int h, double* out) {
+  for (int i = 0; i < 4; ++i) out[i] = NAN;
+  if (w < 3 || h < 3 || w * h > ORC_MAXPIX) return -1;
+  double best = -INFINITY;
+  int bx = 0, by = 0;
+  for (int r = 0; r < h; ++r)
+    for (int c = 0; c < w; ++c) {
+      double acc = 0.0;
+      int cnt = 0;
+      for (int dr = -1; dr <= 1; ++dr)
+        for (int dc = -1; dc <= 1; ++dc) {
+          const int rr = r + dr, cc = c + dc;
+          if (rr < 0 || rr >= h || cc < 0 || cc >= w) continue;
+          acc += g[rr * w + cc];
+          ++cnt;
+        }
+      const double mean = acc / cnt;
+      if (mean > best) {
+        best = mean;
+        bx = c;
+        by = r;
+      }
+    }
+  double lo = g[0], hi = g[0];
+  for (int k = 1; k < w * h; ++k) {
+    lo = g[k] < lo ? g[k] : lo;
+    hi = g[k] > hi ? g[k] : hi;
+  }
+  const double beta0 = lo, alpha0 = hi - lo;
+  const double thr = fma(alpha0, exp(-0.5), beta0);
+  int M = 0;
+  for (int k = 0; k < w * h; ++k) M += g[k] > thr;
+  double s = sqrt(M / M_PI);
+  if (s < 0.5) s = 0.5;
+  out[0] = bx;
+  out[1] = by;
+  out[2] = out[3] = s;
+  return 0;
+}
+
+int orc_peak_init_batch(const void* data, int dtype, const uint8_t* sizes,
+                        const int64_t* offsets, int64_t n, double* out) {
+  double g[ORC_MAXPIX];
+  for (int64_t s = 0; s < n; ++s) {
+    const int w = sizes[4 * s], h = sizes[4 * s + 1];
+    if (w < 3 || h < 3 || w * h > ORC_MAXPIX) {
+      for (int i = 0; i < 4; ++i) out[4 * s + i] = NAN;
+      continue;
+    }
+    for (int k = 0; k < w * h; ++k)
+      g[k] = dtype == 0 ? (double)((const uint16_t*)data)[offsets[s] + k]
+                        : (double)((const float*)data)[offsets[s] + k];
+    orc_peak_init(g, w, h, out + 4 * s);
+  }
+  return 0;
+}

@@ -21,6 +21,10 @@
  *              hand-built images with known centroid / moments, the flat and
  *              single-pixel degenerate cases, and an independent vectorised
  *              implementation of the same estimate.
+ *   orc_peak_init  (the paper's start values, Results section) pinned by a
+ *              lone bright pixel (window ties), a flat image, plateaus of known
+ *              area, a library 2-D convolution with first-occurrence argmax,
+ *              and the Table 1 statistics it feeds.
  */
 #ifndef SPOTFIT_ORACLE_H
 #define SPOTFIT_ORACLE_H
@@ -100,6 +104,16 @@ int orc_moment_init(const double* g, int w, int h, int model, double* out);
 /* The same for a ragged batch in the library's layout; out double[n][4]. */
 int orc_moment_init_batch(const void* data, int dtype, const uint8_t* sizes,
                           const int64_t* offsets, int64_t n, double* out);
+
+/* The paper's start values (Results section): centre = brightest pixel of the
+ * 3 x 3 moving average (mean over the in-ROI part of the window; first in
+ * row-major order on ties); sigma = sqrt(M / pi), M = raw pixels above
+ * (max - min) exp(-1/2) + min (fused multiply-add), at least 0.5.  out = (x, y,
+ * sigma, sigma); returns 0, or -1 (NaN out) for w or h < 3 or more than 1024
+ * pixels. */
+int orc_peak_init(const double* g, int w, int h, double* out);
+int orc_peak_init_batch(const void* data, int dtype, const uint8_t* sizes,
+                        const int64_t* offsets, int64_t n, double* out);
 
 #ifdef __cplusplus
 }

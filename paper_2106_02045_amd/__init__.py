@@ -28,7 +28,7 @@ EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_
             "spotfit_serve_submit", "spotfit_serve_poll", "spotfit_serve_wait",
             "spotfit_serve_stats", "spotfit_serve_destroy", "spotfit_serve_replay",
             "spotfit_serve_last_error", "spotfit_get_stats", "spotfit_autotune",
-            "spotfit_moment_init"]
+            "spotfit_moment_init", "spotfit_peak_init", "spotfit_serve_track"]
 E_AGAIN = -6
 
 
@@ -56,6 +56,22 @@ class Options(ctypes.Structure):
     ]
 
 
+class Drift(ctypes.Structure):
+    """Mirror of spotfit_drift_t."""
+    _fields_ = [
+        ("dx", ctypes.c_float),
+        ("dy", ctypes.c_float),
+        ("mean_dx", ctypes.c_float),
+        ("mean_dy", ctypes.c_float),
+        ("n_used", ctypes.c_int32),
+        ("n_frames", ctypes.c_int32),
+    ]
+
+
+DRIFT_DTYPE = [("dx", "<f4"), ("dy", "<f4"), ("mean_dx", "<f4"), ("mean_dy", "<f4"),
+               ("n_used", "<i4"), ("n_frames", "<i4")]
+
+
 class Frame(ctypes.Structure):
     """Mirror of spotfit_frame_t (host pointers)."""
     _fields_ = [
@@ -68,6 +84,7 @@ class Frame(ctypes.Structure):
         ("chi2_out", ctypes.c_void_p),
         ("iters_out", ctypes.c_void_p),
         ("status_out", ctypes.c_void_p),
+        ("drift_out", ctypes.c_void_p),
     ]
 
 
@@ -150,6 +167,8 @@ def lib():
         L.spotfit_serve_wait.argtypes = [vp, u64]
         L.spotfit_serve_wait.restype = ctypes.c_int
         L.spotfit_serve_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+        L.spotfit_serve_track.argtypes = [vp, i32, vp, i32]
+        L.spotfit_serve_track.restype = ctypes.c_int
         L.spotfit_serve_stats.restype = ctypes.c_int
         L.spotfit_serve_destroy.argtypes = [vp]
         L.spotfit_serve_destroy.restype = None
@@ -160,6 +179,8 @@ def lib():
         L.spotfit_moment_init.argtypes = [vp, vp, i32, vp, vp, i64, ctypes.POINTER(Options), vp,
                                           vp]
         L.spotfit_moment_init.restype = ctypes.c_int
+        L.spotfit_peak_init.argtypes = L.spotfit_moment_init.argtypes
+        L.spotfit_peak_init.restype = ctypes.c_int
         L.spotfit_get_stats.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(Stats), vp]
         L.spotfit_get_stats.restype = ctypes.c_int
         L.spotfit_autotune.argtypes = [vp, vp, i32, vp, vp, vp, i64, ctypes.POINTER(Options),
@@ -295,9 +316,7 @@ class Context:
                       chosen_plan=rep.plan_id[rep.chosen])
         return out, report
 
-    def moment_init(self, data, sizes, offsets, opts: Optional[Options] = None, out=None,
-                    stream=None):
-        """Start values on the device (spotfit_moment_init); returns float32 [n, 4]."""
+    def _start_values(self, fn: str, data, sizes, offsets, opts, out, stream):
         import torch
         n = int(sizes.shape[0])
         dt = U16 if data.dtype == torch.uint16 else F32 if data.dtype == torch.float32 else None
@@ -306,15 +325,32 @@ class Context:
         for name, t, want in (("sizes", sizes, torch.uint8), ("offsets", offsets, torch.int64)):
             if t.dtype != want or not t.is_contiguous() or t.device != data.device:
                 raise TypeError(f"{name} must be a contiguous {want} tensor on {data.device}")
+        if tuple(sizes.shape) != (n, 4) or tuple(offsets.shape) != (n,):
+            raise ValueError("sizes must be [n, 4] and offsets [n]")
         if out is None:
             out = torch.empty((n, 4), dtype=torch.float32, device=data.device)
+        elif (out.dtype != torch.float32 or tuple(out.shape) != (n, 4) or not out.is_contiguous()
+              or out.device != data.device):
+            raise TypeError(f"out must be a contiguous float32 [n, 4] tensor on {data.device}")
         st = stream if stream is not None else torch.cuda.current_stream(data.device)
-        rc = lib().spotfit_moment_init(self._h, data.data_ptr(), dt, sizes.data_ptr(),
-                                       offsets.data_ptr(), n,
-                                       ctypes.byref(opts) if opts is not None else None,
-                                       out.data_ptr(), st.cuda_stream)
-        _check(rc, "spotfit_moment_init")
+        rc = getattr(lib(), fn)(self._h, data.data_ptr(), dt, sizes.data_ptr(),
+                                offsets.data_ptr(), n,
+                                ctypes.byref(opts) if opts is not None else None,
+                                out.data_ptr(), st.cuda_stream)
+        _check(rc, fn)
         return out
+
+    def moment_init(self, data, sizes, offsets, opts: Optional[Options] = None, out=None,
+                    stream=None):
+        """Centroid / second-moment start values on the device (spotfit_moment_init);
+        returns float32 [n, 4]."""
+        return self._start_values("spotfit_moment_init", data, sizes, offsets, opts, out, stream)
+
+    def peak_init(self, data, sizes, offsets, opts: Optional[Options] = None, out=None,
+                  stream=None):
+        """The paper's start values on the device (spotfit_peak_init): brightest pixel of
+        the 3x3 moving average, sigma = sqrt(M / pi); returns float32 [n, 4]."""
+        return self._start_values("spotfit_peak_init", data, sizes, offsets, opts, out, stream)
 
     def stats(self, out, stream=None):
         """Stop reasons, iteration histogram and evaluation totals of a fit's outputs."""
@@ -354,10 +390,28 @@ class Server:
         self._h = h
         self._keep = {}
 
+    def track(self, ref_xy, window: int):
+        """Turn on drift tracking (spotfit_serve_track): ref_xy [M, 2] reference marker
+        positions; frames submitted with track=True then carry outputs["drift"].
+        ref_xy None turns it off.  Call with no frame in flight."""
+        import numpy as np
+        if ref_xy is None:
+            m, ptr = 0, None
+        else:
+            ref = np.ascontiguousarray(ref_xy, dtype=np.float32)
+            if ref.ndim != 2 or ref.shape[1] != 2:
+                raise ValueError("ref_xy must be [n_markers, 2]")
+            m, ptr = int(ref.shape[0]), ref.ctypes.data
+        rc = lib().spotfit_serve_track(self._h, m, ptr, int(window))
+        if rc != 0:
+            raise SpotfitError(f"spotfit_serve_track failed with {rc}: "
+                               f"{lib().spotfit_serve_last_error().decode(errors='replace')}")
+
     @staticmethod
-    def make_frame(data, sizes, init):
+    def make_frame(data, sizes, init, track: bool = False):
         """Build a spotfit_frame_t (and its output arrays) from numpy arrays.
-        init None: start values computed on the device."""
+        init None: start values computed on the device.  track: a tracked frame,
+        whose drift record lands in outputs["drift"] (a structured array of one)."""
         import numpy as np
         data = np.ascontiguousarray(data)
         sizes = np.ascontiguousarray(sizes, dtype=np.uint8)
@@ -366,15 +420,18 @@ class Server:
         n = int(sizes.shape[0])
         outs = dict(params=np.zeros((n, 6), np.float32), chi2=np.zeros(n, np.float32),
                     iters=np.zeros(n, np.int32), status=np.zeros(n, np.int32))
+        if track:
+            outs["drift"] = np.zeros(1, dtype=DRIFT_DTYPE)
         f = Frame(data.ctypes.data, sizes.ctypes.data,
                   init.ctypes.data if init is not None else None, n,
                   U16 if data.dtype == np.uint16 else F32, outs["params"].ctypes.data,
-                  outs["chi2"].ctypes.data, outs["iters"].ctypes.data, outs["status"].ctypes.data)
+                  outs["chi2"].ctypes.data, outs["iters"].ctypes.data, outs["status"].ctypes.data,
+                  outs["drift"].ctypes.data if track else None)
         return f, (data, sizes, init), outs
 
-    def submit(self, data, sizes, init, arrival_ns: int = 0):
+    def submit(self, data, sizes, init, arrival_ns: int = 0, track: bool = False):
         """Returns (ticket, outputs) or None when the frame is not admitted now."""
-        f, ins, outs = self.make_frame(data, sizes, init)
+        f, ins, outs = self.make_frame(data, sizes, init, track)
         t = ctypes.c_uint64()
         rc = lib().spotfit_serve_submit(self._h, ctypes.byref(f), int(arrival_ns), ctypes.byref(t))
         if rc == E_AGAIN:
@@ -395,7 +452,8 @@ class Server:
         return lib().spotfit_serve_poll(self._h, int(ticket))
 
     def replay(self, frames, arrival_offset_ns):
-        """frames: list of (data, sizes, init); arrival offsets in ns.  Returns outputs."""
+        """frames: list of (data, sizes, init[, track]); arrival offsets in ns.  Returns
+        outputs."""
         import numpy as np
         built = [self.make_frame(*fr) for fr in frames]
         arr = (Frame * len(built))(*[b[0] for b in built])

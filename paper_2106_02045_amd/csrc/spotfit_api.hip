@@ -46,6 +46,9 @@ int fail_hip(hipError_t e, const char* where) {
   return SPOTFIT_E_HIP;
 }
 
+int fail(int code, const std::string& what) { return fail(code, what.c_str()); }
+int fail_hip(hipError_t e, const std::string& where) { return fail_hip(e, where.c_str()); }
+
 int ppl_index(int ppl) {
   switch (ppl) {
     case 1: return 0;
@@ -408,12 +411,12 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                     status_out, evals_out, stream);
 }
 
-int spotfit_moment_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+static int start_values(int method, const char* what, const void* data, int32_t dtype,
                         const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n,
                         const spotfit_options_t* opt, float* init_out, void* stream) {
-  if (!ctx) return fail(SPOTFIT_E_NULL, "moment_init: NULL context");
-  if (n < 0) return fail(SPOTFIT_E_ARG, "moment_init: n_spots < 0");
-  if (dtype != SPOTFIT_U16 && dtype != SPOTFIT_F32) return fail(SPOTFIT_E_ARG, "moment_init: unknown dtype");
+  if (n < 0) return fail(SPOTFIT_E_ARG, std::string(what) + ": n_spots < 0");
+  if (dtype != SPOTFIT_U16 && dtype != SPOTFIT_F32)
+    return fail(SPOTFIT_E_ARG, std::string(what) + ": unknown dtype");
   spotfit_options_t o;
   if (opt) {
     o = *opt;
@@ -423,11 +426,28 @@ int spotfit_moment_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
   const int rc = spotfit_validate_options(&o);
   if (rc != SPOTFIT_OK) return rc;
   if (n == 0) return SPOTFIT_OK;
-  if (!data || !sizes || !offsets || !init_out) return fail(SPOTFIT_E_NULL, "moment_init: NULL array");
-  const hipError_t e = sf::launch_moment_init(data, dtype, sizes, offsets, n, o.max_side,
-                                              o.max_pixels, init_out, (hipStream_t)stream);
-  if (e != hipSuccess) return fail_hip(e, "moment init kernel launch");
+  if (!data || !sizes || !offsets || !init_out)
+    return fail(SPOTFIT_E_NULL, std::string(what) + ": NULL array");
+  const hipError_t e = sf::launch_start_values(method, data, dtype, sizes, offsets, n, o.max_side,
+                                               o.max_pixels, init_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, std::string(what) + " kernel launch");
   return SPOTFIT_OK;
+}
+
+int spotfit_moment_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                        const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n,
+                        const spotfit_options_t* opt, float* init_out, void* stream) {
+  if (!ctx) return fail(SPOTFIT_E_NULL, "moment_init: NULL context");
+  return start_values(sf::kInitMoments, "moment_init", data, dtype, sizes, offsets, n, opt,
+                      init_out, stream);
+}
+
+int spotfit_peak_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                      const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n,
+                      const spotfit_options_t* opt, float* init_out, void* stream) {
+  if (!ctx) return fail(SPOTFIT_E_NULL, "peak_init: NULL context");
+  return start_values(sf::kInitPeak, "peak_init", data, dtype, sizes, offsets, n, opt, init_out,
+                      stream);
 }
 
 int spotfit_get_stats(spotfit_ctx_t* ctx, const int32_t* status, const int32_t* iters,

@@ -11,10 +11,15 @@
 // sigma_x = sqrt(var_x), sigma_y = sqrt(var_y); sigmas clamped to
 // [0.8, max(w, h) / 4]; with no positive weight: the ROI centre and sigma 1.5.
 //
+// A second estimate is the recipe the paper gives for its accuracy runs
+// (Results section): centre = brightest pixel of the 3 x 3 moving average,
+// sigma = sqrt(M / pi) with M the pixels above alpha0 exp(-1/2) + beta0.
+//
 // Mapping: a group of L lanes per spot, lane l owning the columns l + L*j as in
-// the fit kernel.  The ring median is a radix select over order-preserving
-// 32-bit keys of the ring values (each lane holds every L-th ring pixel; one
-// group count per key bit), so no sort and no LDS are needed.
+// the fit kernel; groups step over the spots with a grid stride.  The ring
+// median is a radix select over order-preserving 32-bit keys of the ring values
+// (each lane holds every L-th ring pixel; one group count per key bit), so no
+// sort and no LDS are needed.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,29 +46,52 @@ __device__ __forceinline__ float load_px(const void* data, int dtype, int64_t i)
                               : static_cast<const float*>(data)[i];
 }
 
+// Shapes a fit with these limits accepts (the others get NaN start values).
+template <int HM>
+__device__ __forceinline__ bool usable(const spotfit_shape_t& sh, int max_side, int max_pixels) {
+  const int w = sh.w, h = sh.h;
+  return !(w < 3 || h < 3 || w > HM || h > HM || w > max_side || h > max_side ||
+           w * h > max_pixels || (sh.model != SPOTFIT_SYM && sh.model != SPOTFIT_ELL));
+}
+
+__device__ __forceinline__ void write_nan(float* out, int64_t s) {
+  const float nanf = __builtin_nanf("");
+  for (int q = 0; q < 4; ++q) out[4 * s + q] = nanf;
+}
+
+template <int L, int CPL>
+__device__ __forceinline__ void moment_init_spot(const void* data, int dtype, const spotfit_shape_t sh,
+                                                 int64_t off, int li, float* o4);
+
 template <int L, int CPL>
 __global__ __launch_bounds__(64) void moment_init_kernel(const void* data, int dtype,
                                                          const spotfit_shape_t* sizes,
                                                          const int64_t* offsets, int64_t n,
                                                          int max_side, int max_pixels,
                                                          float* out) {
-  constexpr int HM = L * CPL;
-  constexpr int RM = (4 * HM + L - 1) / L;  // ring pixels per lane, at most
   const int lane = __lane_id();
   const int li = lane % L;
-  const int64_t s = (int64_t)blockIdx.x * (64 / L) + lane / L;
-  if (s >= n) return;  // whole groups leave together
-  const spotfit_shape_t sh = sizes[s];
-  const int w = sh.w, h = sh.h;
-  if (w < 3 || h < 3 || w > HM || h > HM || w > max_side || h > max_side || w * h > max_pixels ||
-      (sh.model != SPOTFIT_SYM && sh.model != SPOTFIT_ELL)) {
-    if (li == 0) {
-      const float nanf = __builtin_nanf("");
-      for (int q = 0; q < 4; ++q) out[4 * s + q] = nanf;
+  const int64_t stride = (int64_t)gridDim.x * (64 / L);
+  // s is the same on every lane of a group, so groups stay whole in the loop
+  for (int64_t s = (int64_t)blockIdx.x * (64 / L) + lane / L; s < n; s += stride) {
+    const spotfit_shape_t sh = sizes[s];
+    if (!usable<L * CPL>(sh, max_side, max_pixels)) {
+      if (li == 0) write_nan(out, s);
+      continue;
     }
-    return;
+    float o[4];
+    moment_init_spot<L, CPL>(data, dtype, sh, offsets[s], li, o);
+    if (li == 0)
+      for (int q = 0; q < 4; ++q) out[4 * s + q] = o[q];
   }
-  const int64_t off = offsets[s];
+}
+
+template <int L, int CPL>
+__device__ __forceinline__ void moment_init_spot(const void* data, int dtype, const spotfit_shape_t sh,
+                                                 int64_t off, int li, float* o4) {
+  constexpr int HM = L * CPL;
+  constexpr int RM = (4 * HM + L - 1) / L;  // ring pixels per lane, at most
+  const int w = sh.w, h = sh.h;
 
   // ---- background: median of the border ring ----
   const int nr = 2 * (w + h - 2);
@@ -168,27 +196,167 @@ __global__ __launch_bounds__(64) void moment_init_kernel(const void* data, int d
     o[2] = sx < lo ? lo : (sx > hi ? hi : sx);
     o[3] = sy < lo ? lo : (sy > hi ? hi : sy);
   }
-  if (li == 0)
-    for (int q = 0; q < 4; ++q) out[4 * s + q] = float(o[q]);
+  for (int q = 0; q < 4; ++q) o4[q] = float(o[q]);
+}
+
+// ---------------------------------------------------------------------------
+// The paper's start values.  Per own pixel the 3 x 3 window sum is formed in
+// double from the pixel's column and its two neighbours (clamped loads, masked
+// outside the ROI) and divided by the number of in-ROI window pixels; the sums
+// are exact for 16-bit pixels (and for 32-bit float pixels within 2^26 of each
+// other), so their order does not matter.  The group keeps the largest mean
+// and, among equal means, the smallest row-major index.
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ __forceinline__ double gmax_d(double v) {
+  if constexpr (L >= 2) v = fmax(v, dpp_mov<0xB1>(v));
+  if constexpr (L >= 4) v = fmax(v, dpp_mov<0x4E>(v));
+  if constexpr (L >= 8) v = fmax(v, dpp_mov<0x141>(v));
+  if constexpr (L >= 16) v = fmax(v, dpp_mov<0x140>(v));
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ float gmin_f(float v) {
+  if constexpr (L >= 2) v = fminf(v, dpp_mov<0xB1>(v));
+  if constexpr (L >= 4) v = fminf(v, dpp_mov<0x4E>(v));
+  if constexpr (L >= 8) v = fminf(v, dpp_mov<0x141>(v));
+  if constexpr (L >= 16) v = fminf(v, dpp_mov<0x140>(v));
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ float gmax_f(float v) {
+  if constexpr (L >= 2) v = fmaxf(v, dpp_mov<0xB1>(v));
+  if constexpr (L >= 4) v = fmaxf(v, dpp_mov<0x4E>(v));
+  if constexpr (L >= 8) v = fmaxf(v, dpp_mov<0x141>(v));
+  if constexpr (L >= 16) v = fmaxf(v, dpp_mov<0x140>(v));
+  return v;
+}
+
+constexpr double kExpMinusHalf = 0x1.368b2fc6f960ap-1;  // e^(-1/2), correctly rounded
+constexpr double kPi = 0x1.921fb54442d18p+1;
+
+template <int L, int CPL>
+__global__ __launch_bounds__(64) void peak_init_kernel(const void* data, int dtype,
+                                                       const spotfit_shape_t* sizes,
+                                                       const int64_t* offsets, int64_t n,
+                                                       int max_side, int max_pixels, float* out) {
+  constexpr int HM = L * CPL;
+  const int lane = __lane_id();
+  const int li = lane % L;
+  const int64_t stride = (int64_t)gridDim.x * (64 / L);
+  for (int64_t s = (int64_t)blockIdx.x * (64 / L) + lane / L; s < n; s += stride) {
+    const spotfit_shape_t sh = sizes[s];
+    if (!usable<HM>(sh, max_side, max_pixels)) {
+      if (li == 0) write_nan(out, s);
+      continue;
+    }
+    const int w = sh.w, h = sh.h;
+    const int64_t off = offsets[s];
+    double best = -__builtin_inf();
+    int bk = 0x7fffffff;
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int c = li + L * j;
+      const bool cin = c < w;
+      const int cm = c - 1 < 0 ? 0 : (c - 1 < w ? c - 1 : w - 1);
+      const int cc = c < w ? c : w - 1;
+      const int cp = c + 1 < w ? c + 1 : w - 1;
+      float g0[HM], g1[HM], g2[HM];  // columns c - 1, c, c + 1 (clamped)
+#pragma unroll
+      for (int r = 0; r < HM; ++r) {
+        const int64_t row = off + (int64_t)(r < h ? r : h - 1) * w;
+        g0[r] = load_px(data, dtype, row + cm);
+        g1[r] = load_px(data, dtype, row + cc);
+        g2[r] = load_px(data, dtype, row + cp);
+      }
+      const bool left = c >= 1, right = c + 1 < w;
+      const int ncol = 1 + (left ? 1 : 0) + (right ? 1 : 0);
+#pragma unroll
+      for (int r = 0; r < HM; ++r) {
+        if (!(cin && r < h)) continue;
+        double acc = 0.0;
+        int nrow = 0;
+#pragma unroll
+        for (int d = -1; d <= 1; ++d) {
+          const int rr = r + d;
+          if (rr < 0 || rr >= h) continue;
+          ++nrow;
+          acc += double(g1[rr]);
+          if (left) acc += double(g0[rr]);
+          if (right) acc += double(g2[rr]);
+        }
+        const double mean = acc / double(nrow * ncol);
+        const int k = r * w + c;
+        if (mean > best || (mean == best && k < bk)) {
+          best = mean;
+          bk = k;
+        }
+        lo = fminf(lo, g1[r]);
+        hi = fmaxf(hi, g1[r]);
+      }
+    }
+    const double top = gmax_d<L>(best);
+    bk = (int)gmin_u<L>(best == top ? (uint32_t)bk : 0xFFFFFFFFu);
+    lo = gmin_f<L>(lo);
+    hi = gmax_f<L>(hi);
+    const double beta0 = double(lo), alpha0 = double(hi) - double(lo);
+    const double thr = __builtin_fma(alpha0, kExpMinusHalf, beta0);
+    int m = 0;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int c = li + L * j;
+      if (c >= w) continue;
+#pragma unroll
+      for (int r = 0; r < HM; ++r)
+        if (r < h) m += double(load_px(data, dtype, off + (int64_t)r * w + c)) > thr ? 1 : 0;
+    }
+    m = gsum_i<L>(m);
+    double sig = sqrt(double(m) / kPi);
+    sig = sig < 0.5 ? 0.5 : sig;
+    if (li == 0) {
+      out[4 * s + 0] = float(bk % w);
+      out[4 * s + 1] = float(bk / w);
+      out[4 * s + 2] = float(sig);
+      out[4 * s + 3] = float(sig);
+    }
+  }
 }
 
 }  // namespace ini
 
-hipError_t launch_moment_init(const void* data, int dtype, const spotfit_shape_t* sizes,
-                              const int64_t* offsets, int64_t n, int max_side, int max_pixels,
-                              float* out, hipStream_t st) {
+hipError_t launch_start_values(int method, const void* data, int dtype, const spotfit_shape_t* sizes,
+                               const int64_t* offsets, int64_t n, int max_side, int max_pixels,
+                               float* out, hipStream_t st) {
+  // groups of 4 lanes (2 or 4 columns each) up to 16 pixels a side, 16 lanes beyond
   const int cls = max_side <= 8 ? 0 : max_side <= 16 ? 1 : 2;
   const int per_block = cls == 2 ? 4 : 16;
-  const int64_t blocks = (n + per_block - 1) / per_block;
-  if (cls == 0)
-    hipLaunchKernelGGL((ini::moment_init_kernel<4, 2>), dim3((unsigned)blocks), dim3(64), 0, st,
-                       data, dtype, sizes, offsets, n, max_side, max_pixels, out);
-  else if (cls == 1)
-    hipLaunchKernelGGL((ini::moment_init_kernel<4, 4>), dim3((unsigned)blocks), dim3(64), 0, st,
-                       data, dtype, sizes, offsets, n, max_side, max_pixels, out);
-  else
-    hipLaunchKernelGGL((ini::moment_init_kernel<16, 2>), dim3((unsigned)blocks), dim3(64), 0, st,
-                       data, dtype, sizes, offsets, n, max_side, max_pixels, out);
+  int64_t blocks = (n + per_block - 1) / per_block;
+  blocks = blocks < (1 << 20) ? blocks : (1 << 20);  // the kernels stride over the rest
+  const dim3 grid((unsigned)blocks), block(64);
+  if (method == kInitMoments) {
+    if (cls == 0)
+      hipLaunchKernelGGL((ini::moment_init_kernel<4, 2>), grid, block, 0, st, data, dtype, sizes,
+                         offsets, n, max_side, max_pixels, out);
+    else if (cls == 1)
+      hipLaunchKernelGGL((ini::moment_init_kernel<4, 4>), grid, block, 0, st, data, dtype, sizes,
+                         offsets, n, max_side, max_pixels, out);
+    else
+      hipLaunchKernelGGL((ini::moment_init_kernel<16, 2>), grid, block, 0, st, data, dtype, sizes,
+                         offsets, n, max_side, max_pixels, out);
+  } else {
+    if (cls == 0)
+      hipLaunchKernelGGL((ini::peak_init_kernel<4, 2>), grid, block, 0, st, data, dtype, sizes,
+                         offsets, n, max_side, max_pixels, out);
+    else if (cls == 1)
+      hipLaunchKernelGGL((ini::peak_init_kernel<4, 4>), grid, block, 0, st, data, dtype, sizes,
+                         offsets, n, max_side, max_pixels, out);
+    else
+      hipLaunchKernelGGL((ini::peak_init_kernel<16, 2>), grid, block, 0, st, data, dtype, sizes,
+                         offsets, n, max_side, max_pixels, out);
+  }
   return hipGetLastError();
 }
 

@@ -84,10 +84,12 @@ const void* narrow_mixed_kernel_symbol(int plan);
 hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid,
                                    hipStream_t st);
 
-// Start values from the pixels (centroid / second moments) for spots with sides
-// up to max_side: float[n][4] into out.
-hipError_t launch_moment_init(const void* data, int dtype, const spotfit_shape_t* sizes,
-                              const int64_t* offsets, int64_t n, int max_side, int max_pixels,
-                              float* out, hipStream_t st);
+// Start values from the pixels for spots with sides up to max_side: float[n][4]
+// into out.  kInitMoments: centroid / second moments; kInitPeak: the paper's
+// recipe (brightest pixel of the 3 x 3 moving average, sigma = sqrt(M / pi)).
+enum { kInitMoments = 0, kInitPeak = 1 };
+hipError_t launch_start_values(int method, const void* data, int dtype, const spotfit_shape_t* sizes,
+                               const int64_t* offsets, int64_t n, int max_side, int max_pixels,
+                               float* out, hipStream_t st);
 
 }  // namespace sf

@@ -12,6 +12,11 @@
 // and the frames' ring space is released (oldest first).  Latency is measured
 // from the frame's arrival (submit time, or the scheduled arrival in replay) to
 // the moment its results are in the caller's arrays.
+//
+// Drift tracking (optional): after a launch's fit, the drift pass of its
+// tracked frames runs on the same stream (spotfit_track.hip), chained behind
+// the previous launch's pass by an event so the history is written in
+// submission order; its per-frame records come back with the fit results.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +34,7 @@
 
 #include "spotfit.h"
 #include "spotfit_internal.h"
+#include "spotfit_track.h"
 
 namespace {
 
@@ -59,6 +65,8 @@ struct FrameRec {
   float* chi2 = nullptr;
   int32_t* iters = nullptr;
   int32_t* status = nullptr;
+  int64_t track_q = -1;               // sequence number among tracked frames, or -1
+  spotfit_drift_t* drift = nullptr;   // caller's record for a tracked frame
 };
 
 struct Batch {
@@ -67,6 +75,7 @@ struct Batch {
   uint64_t first_ticket = 0;  // frames [first_ticket, first_ticket + n_frames)
   int n_frames = 0;
   int64_t spot0 = 0, n_spots = 0;
+  int n_tracked = 0;  // tracked frames of the batch, in ticket order
   bool failed = false;
 };
 
@@ -109,6 +118,17 @@ struct spotfit_serve {
   // tickets below this are admitted: the dispatcher polls it without the lock
   std::atomic<uint64_t> admitted_end{1};
 
+  // drift tracking: reference positions and history ring on the device; per
+  // stream, staging for one batch's tracked frames and their drift records
+  int track_markers = 0, track_window = 0;
+  int64_t track_next = 0;  // sequence number of the next tracked frame
+  float* d_ref = nullptr;
+  sf::TrackHist* d_hist = nullptr;
+  std::vector<sf::TrackFrame*> h_tf, d_tf;
+  std::vector<spotfit_drift_t*> h_drift, d_drift;
+  hipEvent_t track_ev = nullptr;  // the last launched drift pass
+  bool track_ev_live = false;
+
   // statistics
   std::vector<uint64_t> lat_ns;
   uint64_t frames_done = 0, spots_done = 0, batches = 0, rejected = 0, frames_failed = 0;
@@ -119,6 +139,7 @@ struct spotfit_serve {
   void run();
   bool launch_ready();
   bool reap();
+  void free_tracking();
 };
 
 namespace {
@@ -231,6 +252,26 @@ bool spotfit_serve::launch_ready() {
     rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0, d_init + 4 * spot0,
                            nsp, &opt, d_params + 6 * spot0, d_chi2 + spot0, d_iters + spot0,
                            d_status + spot0, nullptr, st);
+  int n_tracked = 0;
+  if (e == hipSuccess && rc == SPOTFIT_OK && track_markers > 0) {
+    sf::TrackFrame* tf = h_tf[si];
+    for (uint64_t t = t0; t < t1; ++t) {
+      const FrameRec& f = rec(t);
+      if (f.track_q >= 0) tf[n_tracked++] = sf::TrackFrame{f.spot0, f.track_q};
+    }
+    if (n_tracked > 0) {
+      e = hipMemcpyAsync(d_tf[si], tf, sizeof(sf::TrackFrame) * n_tracked, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess && track_ev_live) e = hipStreamWaitEvent(st, track_ev, 0);
+      if (e == hipSuccess)
+        e = sf::launch_drift_track(d_tf[si], n_tracked, d_params, d_status, d_ref, track_markers,
+                                   d_hist, track_window, d_drift[si], st);
+      if (e == hipSuccess) e = hipEventRecord(track_ev, st);
+      track_ev_live = track_ev_live || e == hipSuccess;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(h_drift[si], d_drift[si], sizeof(spotfit_drift_t) * n_tracked,
+                           hipMemcpyDeviceToHost, st);
+    }
+  }
   if (e == hipSuccess && rc == SPOTFIT_OK)
     e = hipMemcpyAsync(h_params + 6 * spot0, d_params + 6 * spot0, sizeof(float) * 6 * nsp,
                        hipMemcpyDeviceToHost, st);
@@ -246,6 +287,7 @@ bool spotfit_serve::launch_ready() {
   b.n_frames = (int)(t1 - t0);
   b.spot0 = spot0;
   b.n_spots = nsp;
+  b.n_tracked = n_tracked;
   b.failed = !(e == hipSuccess && rc == SPOTFIT_OK);
   if (!b.failed) {
     if (!event_pool.empty()) {
@@ -285,9 +327,14 @@ bool spotfit_serve::reap() {
     if (b.ev) event_pool.push_back(b.ev);
     const uint64_t tnow = now_ns();
     std::lock_guard<std::mutex> lk(mu);
+    int tracked = 0;
     for (int k = 0; k < b.n_frames; ++k) {
       FrameRec& f = rec(b.first_ticket + k);
       if (!b.failed) {
+        if (f.track_q >= 0) {
+          if (f.drift) *f.drift = h_drift[b.stream][tracked];
+          ++tracked;
+        }
         std::memcpy(f.params, h_params + 6 * f.spot0, sizeof(float) * 6 * f.n);
         std::memcpy(f.chi2, h_chi2 + f.spot0, sizeof(float) * f.n);
         if (f.iters) std::memcpy(f.iters, h_iters + f.spot0, sizeof(int32_t) * f.n);
@@ -332,7 +379,66 @@ void spotfit_serve::run() {
   reap();
 }
 
+void spotfit_serve::free_tracking() {
+  if (d_ref) (void)hipFree(d_ref);
+  if (d_hist) (void)hipFree(d_hist);
+  for (auto p : d_tf) (void)hipFree(p);
+  for (auto p : h_tf) (void)hipHostFree(p);
+  for (auto p : d_drift) (void)hipFree(p);
+  for (auto p : h_drift) (void)hipHostFree(p);
+  if (track_ev) (void)hipEventDestroy(track_ev);
+  d_ref = nullptr;
+  d_hist = nullptr;
+  d_tf.clear();
+  h_tf.clear();
+  d_drift.clear();
+  h_drift.clear();
+  track_ev = nullptr;
+  track_ev_live = false;
+  track_markers = 0;
+  track_window = 0;
+}
+
 extern "C" {
+
+int spotfit_serve_track(spotfit_serve_t* sv, int32_t n_markers, const float* ref_xy,
+                        int32_t window) {
+  if (!sv) return serve_fail(SPOTFIT_E_NULL, "serve_track: NULL serving loop");
+  if (n_markers < 0 || n_markers > 65536 || (n_markers > 0 && (window < 1 || window > 65536)))
+    return serve_fail(SPOTFIT_E_ARG, "serve_track: n_markers in [0, 65536], window in [1, 65536]");
+  if (n_markers > 0 && !ref_xy) return serve_fail(SPOTFIT_E_NULL, "serve_track: NULL reference");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->oldest_ticket != sv->next_ticket) return SPOTFIT_E_AGAIN;  // frames in flight
+  (void)hipSetDevice(sv->device);
+  sv->free_tracking();
+  sv->track_next = 0;
+  if (n_markers == 0) return SPOTFIT_OK;
+  const size_t nf = (size_t)sv->max_frames;
+  hipError_t e = hipMalloc((void**)&sv->d_ref, sizeof(float) * 2 * (size_t)n_markers);
+  if (e == hipSuccess) e = hipMalloc((void**)&sv->d_hist, sizeof(sf::TrackHist) * (size_t)window);
+  for (int i = 0; i < sv->n_streams && e == hipSuccess; ++i) {
+    sf::TrackFrame *dt = nullptr, *ht = nullptr;
+    spotfit_drift_t *dd = nullptr, *hd = nullptr;
+    e = hipMalloc((void**)&dt, sizeof(sf::TrackFrame) * nf);
+    if (e == hipSuccess) sv->d_tf.push_back(dt);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ht, sizeof(sf::TrackFrame) * nf, hipHostMallocDefault);
+    if (e == hipSuccess) sv->h_tf.push_back(ht);
+    if (e == hipSuccess) e = hipMalloc((void**)&dd, sizeof(spotfit_drift_t) * nf);
+    if (e == hipSuccess) sv->d_drift.push_back(dd);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&hd, sizeof(spotfit_drift_t) * nf, hipHostMallocDefault);
+    if (e == hipSuccess) sv->h_drift.push_back(hd);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->track_ev, hipEventDisableTiming);
+  if (e == hipSuccess)
+    e = hipMemcpy(sv->d_ref, ref_xy, sizeof(float) * 2 * (size_t)n_markers, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    sv->free_tracking();
+    return serve_fail(SPOTFIT_E_HIP, std::string("serve_track: ") + hipGetErrorString(e));
+  }
+  sv->track_markers = n_markers;
+  sv->track_window = window;
+  return SPOTFIT_OK;
+}
 
 int spotfit_serve_create(spotfit_serve_t** out, int device, const spotfit_options_t* opt,
                          size_t budget, int32_t max_frames, int32_t n_streams) {
@@ -413,6 +519,8 @@ int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_
   for (int64_t i = 0; i < n; ++i) npx += (int64_t)fr->sizes[i].w * fr->sizes[i].h;
   const int64_t bytes = ((npx * esz) + 255) & ~(int64_t)255;
   std::unique_lock<std::mutex> lk(sv->mu);
+  if (fr->drift_out && (sv->track_markers == 0 || n != sv->track_markers))
+    return serve_fail(SPOTFIT_E_ARG, "serve_submit: a tracked frame needs tracking on and one spot per marker");
   const uint64_t t = sv->next_ticket;
   // a free slot, and room in both rings (skipping a ring's tail when the frame
   // does not fit before the wrap)
@@ -443,6 +551,10 @@ int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_
   f.chi2 = fr->chi2_out;
   f.iters = fr->iters_out;
   f.status = fr->status_out;
+  if (fr->drift_out) {
+    f.track_q = sv->track_next++;
+    f.drift = fr->drift_out;
+  }
   sv->pix_head = (sv->pix_head + bytes) % sv->pix_cap;
   sv->spot_head = (sv->spot_head + n) % sv->spot_cap;
   sv->pix_used += f.pix_bytes;
@@ -524,6 +636,7 @@ void spotfit_serve_destroy(spotfit_serve_t* sv) {
   (void)hipSetDevice(sv->device);
   for (auto s : sv->streams) (void)hipStreamSynchronize(s);
   for (auto ev : sv->event_pool) (void)hipEventDestroy(ev);
+  sv->free_tracking();
   for (auto c : sv->ctxs) spotfit_ctx_destroy(c);
   for (auto s : sv->streams) (void)hipStreamDestroy(s);
   free_pair(sv->d_pix, sv->h_pix);

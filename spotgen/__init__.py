@@ -393,3 +393,43 @@ def serve_frames(n_frames: int, fps: float = 1000.0, seed: int = 4,
         frames.append(SpotBatch(pool.data[o0:o1], pool.sizes[s0:s1], pool.offsets[s0:s1] - o0,
                                 pool.init[s0:s1], pool.truth[s0:s1], f"frame{f}"))
     return t, frames
+
+
+def drift_frames(n_frames: int, n_markers: int = 32, side: int = 13, fps: float = 1000.0,
+                 seed: int = 6, walk_sd: float = 0.002, sway: float = 0.3,
+                 sway_period_s: float = 2.0):
+    """Frames of fixed fiducial markers whose sample drifts (the tracking workload).
+
+    Each marker has its own ROI (side x side), sub-ROI position (centre +- 1 px),
+    sigma U[1.5, 2.5], peak U[1000, 5000] and background 150.  The sample moves
+    every marker by the same drift d(f) = random walk (step sd walk_sd px per
+    frame) + a sway of amplitude `sway` px and period sway_period_s at `fps`.
+    Pixels are point-sampled, Poisson noise, uint16.  Returns (ref [M, 2] true
+    marker positions at zero drift, drift [F, 2] true drift per frame, list of
+    per-frame SpotBatch with the markers in order and moment start values).
+    """
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 5151])))
+    M = int(n_markers)
+    c0 = (side - 1) / 2.0
+    ref = c0 + rng.uniform(-1.0, 1.0, size=(M, 2))
+    sig = rng.uniform(1.5, 2.5, size=M)
+    alpha = rng.uniform(1000.0, 5000.0, size=M)
+    beta = np.full(M, 150.0)
+    steps = rng.normal(0.0, walk_sd, size=(n_frames, 2))
+    walk = np.cumsum(steps, axis=0)
+    ph = 2.0 * math.pi * np.arange(n_frames) / (fps * sway_period_s)
+    drift = walk + sway * np.stack([np.sin(ph), 0.5 * np.sin(2.0 * ph + 1.0)], axis=1)
+    frames = []
+    sizes = np.zeros((M, 4), dtype=np.uint8)
+    sizes[:, 0] = sizes[:, 1] = side
+    offs = np.arange(M, dtype=np.int64) * side * side
+    for f in range(n_frames):
+        cx = ref[:, 0] + drift[f, 0]
+        cy = ref[:, 1] + drift[f, 1]
+        lam = _render_group(side, side, cx, cy, sig, sig, alpha, beta).reshape(-1)
+        g = np.clip(np.rint(rng.poisson(lam).astype(np.float64)), 0, 65535)
+        data = g.astype(np.uint16)
+        init = moment_init(data.astype(np.float64).reshape(M, side, side), SYM).astype(np.float32)
+        truth = np.stack([cx, cy, sig, sig, alpha, beta], axis=1)
+        frames.append(SpotBatch(data, sizes.copy(), offs.copy(), init, truth, f"drift{f}"))
+    return ref, drift, frames

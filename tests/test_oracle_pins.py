@@ -395,3 +395,124 @@ def test_moment_init_matches_the_vectorised_estimate():
 def test_moment_init_rejects_unusable_shapes():
     assert np.all(np.isnan(oracle.moment_init(np.ones(6), 2, 3, 0)))
     assert np.all(np.isnan(oracle.moment_init(np.ones(25), 5, 5, 7)))
+
+
+# ---------------------------------------------------------------------------
+# The paper's start values (Results section): 3x3 moving average, brightest
+# smoothed pixel, sigma = sqrt(M / pi).  Pinned by images whose smoothed
+# maximum and above-threshold count are known by hand, and by a library 2-D
+# convolution with numpy's first-occurrence argmax.
+# ---------------------------------------------------------------------------
+def test_peak_init_lone_bright_pixel():
+    s1 = math.sqrt(1.0 / math.pi)
+    g = np.full((9, 11), 100.0)
+    g[4, 5] = 1000.0
+    # every full window holding the bright pixel has mean 200: nine ties, the
+    # first in row-major order is the window centred one up and one left
+    np.testing.assert_array_equal(oracle.peak_init(g, 11, 9), [4.0, 3.0, s1, s1])
+    g = np.full((9, 11), 100.0)
+    g[0, 5] = 1000.0
+    # on the top edge the windows hold six pixels: mean 250 beats the full ones' 200
+    np.testing.assert_array_equal(oracle.peak_init(g, 11, 9), [4.0, 0.0, s1, s1])
+    g = np.full((9, 11), 100.0)
+    g[8, 10] = 1000.0
+    # in a corner the window holds four pixels: mean 325
+    np.testing.assert_array_equal(oracle.peak_init(g, 11, 9), [10.0, 8.0, s1, s1])
+
+
+def test_peak_init_flat_image():
+    # no pixel exceeds the threshold (= the flat value): M = 0, sigma floored at 0.5
+    np.testing.assert_array_equal(oracle.peak_init(np.full((7, 9), 42.0), 9, 7),
+                                  [0.0, 0.0, 0.5, 0.5])
+
+
+def test_peak_init_plateaus_of_known_area():
+    g = np.full((9, 13), 100.0)
+    g[3:6, 5:8] = 500.0  # 3x3 block centred on (x=6, y=4): its centre alone averages 500
+    np.testing.assert_array_equal(oracle.peak_init(g, 13, 9),
+                                  [6.0, 4.0, 3.0 / math.sqrt(math.pi), 3.0 / math.sqrt(math.pi)])
+    g = np.full((9, 13), 100.0)
+    g[2:4, 7:9] = 500.0  # 2x2 block: its four pixels tie, the first is its top-left corner
+    np.testing.assert_array_equal(oracle.peak_init(g, 13, 9),
+                                  [7.0, 2.0, 2.0 / math.sqrt(math.pi), 2.0 / math.sqrt(math.pi)])
+
+
+def test_peak_init_threshold():
+    # min 0, max 1000: threshold 1000 exp(-1/2) = 606.53...; 607 counts, 606 does not
+    g = np.zeros((8, 8))
+    g[0, 0] = 1000.0
+    g[5, 1:4] = 607.0
+    g[6, 1:6] = 606.0
+    out = oracle.peak_init(g, 8, 8)
+    assert out[2] == math.sqrt(4.0 / math.pi)
+
+
+def test_peak_init_matches_library_convolution():
+    from scipy.signal import convolve2d
+    k = np.ones((3, 3))
+    for S, sig, bg in ((4, 400, 40), (9, 400, 40), (11, 1600, 0), (21, 1000, 441)):
+        b = spotgen.paper_protocol(300, S, sig, bg, seed=5)
+        mine = oracle.peak_init_batch(b)
+        for s in range(b.n):
+            img = b.spot(s).reshape(S, S).astype(np.float64)
+            sm = convolve2d(img, k, mode="same") / convolve2d(np.ones_like(img), k, mode="same")
+            y0, x0 = np.divmod(int(np.argmax(sm)), S)
+            lo, hi = img.min(), img.max()
+            M = int((img > (hi - lo) * math.exp(-0.5) + lo).sum())
+            sg = max(math.sqrt(M / math.pi), 0.5)
+            np.testing.assert_array_equal(mine[s], [x0, y0, sg, sg])
+
+
+def test_peak_init_matches_the_generator_recipe():
+    # the generator's vectorised version of the same recipe (the start values of
+    # the paper-protocol batches), an independent implementation
+    for S in (5, 9, 16, 32):
+        b = spotgen.paper_protocol(500, S, 400, 40, seed=6)
+        np.testing.assert_array_equal(oracle.peak_init_batch(b).astype(np.float32), b.init)
+
+
+def test_peak_init_rejects_unusable_shapes():
+    assert np.all(np.isnan(oracle.peak_init(np.ones(6), 2, 3)))
+    assert np.all(np.isnan(oracle.peak_init(np.ones(33 * 32), 33, 32)))
+
+
+# ---------------------------------------------------------------------------
+# Drift tracking of fiducial markers (averaging positions over markers and
+# frames, Introduction): pinned by exact shifts, excluded markers and a linear
+# drift whose window means are known in closed form.
+# ---------------------------------------------------------------------------
+def _marker_frames(F, M, shift):
+    ref = np.stack([np.arange(M) * 0.5 + 3.0, np.arange(M) * 0.25 + 4.0], axis=1)
+    p = np.zeros((F, M, 6))
+    for f in range(F):
+        p[f, :, 0] = ref[:, 0] + shift[f][0]
+        p[f, :, 1] = ref[:, 1] + shift[f][1]
+    return p, np.full((F, M), oracle.MIN_DELTA), ref
+
+
+def test_drift_exact_shift_and_excluded_markers():
+    p, st, ref = _marker_frames(3, 10, [(0.25, -0.5)] * 3)
+    # markers whose fit did not stop on a convergence test do not count
+    st[1, 3] = oracle.NOT_CONVERGED
+    p[1, 3, 0] += 5.0
+    st[1, 4] = oracle.MAX_ITER
+    p[1, 4, 1] -= 7.0
+    st[2, :] = oracle.BAD_INPUT  # a frame with no usable marker
+    out = oracle.drift_track(p, st, ref, window=8)
+    np.testing.assert_array_equal(out[0], [0.25, -0.5, 0.25, -0.5, 10, 1])
+    np.testing.assert_array_equal(out[1], [0.25, -0.5, 0.25, -0.5, 8, 2])
+    assert np.all(np.isnan(out[2, :2])) and out[2, 4] == 0
+    np.testing.assert_array_equal(out[2, 2:4], [0.25, -0.5])  # the window keeps the others
+    assert out[2, 5] == 2
+
+
+def test_drift_window_mean_of_linear_drift():
+    F, W = 12, 4
+    p, st, ref = _marker_frames(F, 6, [(0.125 * f, -0.0625 * f) for f in range(F)])
+    out = oracle.drift_track(p, st, ref, window=W)
+    for f in range(F):
+        k = min(W, f + 1)
+        mean_f = f - (k - 1) / 2.0  # mean of f-k+1 .. f
+        assert out[f, 2] == pytest.approx(0.125 * mean_f, abs=1e-15)
+        assert out[f, 3] == pytest.approx(-0.0625 * mean_f, abs=1e-15)
+        assert out[f, 5] == k
