@@ -408,7 +408,8 @@ int spotfit_serve_track(spotfit_serve_t* sv, int32_t n_markers, const float* ref
     return serve_fail(SPOTFIT_E_ARG, "serve_track: n_markers in [0, 65536], window in [1, 65536]");
   if (n_markers > 0 && !ref_xy) return serve_fail(SPOTFIT_E_NULL, "serve_track: NULL reference");
   std::lock_guard<std::mutex> lk(sv->mu);
-  if (sv->oldest_ticket != sv->next_ticket) return SPOTFIT_E_AGAIN;  // frames in flight
+  for (uint64_t t = sv->oldest_ticket; t < sv->next_ticket; ++t)  // frames in flight
+    if (sv->rec(t).state != kDone && sv->rec(t).state != kFailed) return SPOTFIT_E_AGAIN;
   (void)hipSetDevice(sv->device);
   sv->free_tracking();
   sv->track_next = 0;

@@ -10,6 +10,11 @@ admitted frames into the next launch and overlaps launches on several streams.
 Per-frame latency = arrival -> results in the caller's host arrays.  Prints one
 JSON line with p50 / p99 latency and sustained fits/s, and checks that frames
 fitted in the mix give the same bits as the same spots fitted alone.
+
+--track M: instead, every frame holds the same M markers (13x13 ROIs) of a
+drifting sample (random walk plus sway), and the loop tracks the drift on the
+device (spotfit_serve_track, window --window frames); the line then also gives
+the tracked drift's error against the true drift.
 """
 from __future__ import annotations
 
@@ -40,6 +45,8 @@ def main(argv=None):
                     help="lane mapping of the fit (latency: one lane per column)")
     ap.add_argument("--device-init", action="store_true",
                     help="frames carry no start values: the loop computes them on the device")
+    ap.add_argument("--track", type=int, default=0, help="markers per frame of a tracked sample")
+    ap.add_argument("--window", type=int, default=16, help="frames in the tracked drift mean")
     a = ap.parse_args(argv)
 
     import torch
@@ -48,16 +55,25 @@ def main(argv=None):
     import spotgen
 
     t0 = time.time()
-    arrivals, frames = spotgen.serve_frames(a.frames, fps=a.fps, seed=a.seed, threads=16)
+    if a.track > 0:
+        ref, truth_drift, frames = spotgen.drift_frames(a.frames, n_markers=a.track, side=13,
+                                                        fps=a.fps, seed=a.seed)
+        gaps = np.random.default_rng(a.seed).exponential(1.0 / a.fps, size=a.frames)
+        arrivals = np.cumsum(gaps)
+    else:
+        arrivals, frames = spotgen.serve_frames(a.frames, fps=a.fps, seed=a.seed, threads=16)
     gen_s = time.time() - t0
     opts = sf.default_options(max_side=21, schedule=(sf.SCHEDULE_MIXED if a.schedule == "mixed"
                                                      else sf.SCHEDULE_UNIFORM),
                               plan_hint=(sf.PLAN_LATENCY if a.plan == "latency" else sf.PLAN_THROUGHPUT))
     srv = sf.Server(0, opts, device_mem_budget=a.budget_mb << 20, max_frames=a.max_frames,
                     n_streams=a.streams)
+    if a.track > 0:
+        srv.track(ref, a.window)
     offs = np.round((arrivals - arrivals[0]) * 1e9).astype(np.uint64)
     w0 = time.perf_counter()
-    outs = srv.replay([(f.data, f.sizes, None if a.device_init else f.init) for f in frames], offs)
+    outs = srv.replay([(f.data, f.sizes, None if a.device_init else f.init, a.track > 0)
+                       for f in frames], offs)
     wall = time.perf_counter() - w0
     st = srv.stats()
     srv.close()
@@ -81,6 +97,18 @@ def main(argv=None):
         mismatched += int(not same)
 
     spots = int(sum(f.n for f in frames))
+    tracking = None
+    if a.track > 0:
+        got = np.concatenate([o["drift"] for o in outs])
+        W = a.window
+        tw = np.stack([truth_drift[max(0, f - W + 1):f + 1].mean(axis=0) for f in range(len(frames))])
+        mean_err = np.stack([got["mean_dx"], got["mean_dy"]], axis=1) - tw
+        frame_err = np.stack([got["dx"], got["dy"]], axis=1) - truth_drift
+        tracking = {"markers": a.track, "window": W,
+                    "rms_frame_drift_error_px": float(np.sqrt(np.nanmean(frame_err ** 2))),
+                    "rms_tracked_drift_error_px": float(np.sqrt(np.nanmean(mean_err[W:] ** 2))),
+                    "drift_range_px": float(np.ptp(truth_drift)),
+                    "frames_without_marker": int((got["n_used"] == 0).sum())}
     rec = {
         "metric": "p99 frame latency",
         "value": st["latency_p99_us"],
@@ -105,9 +133,12 @@ def main(argv=None):
         "start_values": "device" if a.device_init else "host",
         "plan": a.plan,
         "alone_vs_mix": {"frames_checked": int(len(check)), "frames_differing": mismatched},
+        "tracking": tracking,
         "data": "synthetic",
-        "config": {"workload": "serve_fiducials", "frames": a.frames, "fps": a.fps,
-                   "spots_per_frame": "U{20..200}", "roi_sides": [9, 13, 17, 21]},
+        "config": ({"workload": "drift_markers", "frames": a.frames, "fps": a.fps,
+                    "spots_per_frame": a.track, "roi_sides": [13]} if a.track > 0 else
+                   {"workload": "serve_fiducials", "frames": a.frames, "fps": a.fps,
+                    "spots_per_frame": "U{20..200}", "roi_sides": [9, 13, 17, 21]}),
         "gen_s": gen_s,
     }
     print(json.dumps(rec))

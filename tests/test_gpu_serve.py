@@ -148,3 +148,57 @@ def test_latency_plan_in_serving_matches_direct_calls(sf):
     r = oracle.fit_batch(frames[0], oracle.default_opts(), threads=4)
     c = compare(outs[0], r, chi_band=1e-11, step_band=1e-9)
     assert c["strict_mismatch"] == 0 and c["tol_fail_same"] == 0
+
+
+def _drift_close(gpu, ref):
+    """float32 roundings of two double-precision means summed in different orders:
+    equal or one float32 step apart (NaN where the oracle has NaN)."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(gpu), nan)
+    step = np.spacing(np.abs(ref[~nan]).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(gpu[~nan] - ref[~nan]) <= 1.01 * step + 1e-12)
+
+
+@pytest.mark.parametrize("fps,streams", [(1000.0, 1), (40000.0, 3)])
+def test_drift_tracking_matches_oracle(sf, fps, streams):
+    # markers of a drifting sample fitted in the serving loop; the device's drift
+    # records against the oracle's drift over the same fitted positions, and the
+    # tracked drift against the true one
+    ref, drift, frames = spotgen.drift_frames(400, n_markers=32, side=13, seed=21)
+    ref = ref.astype(np.float32)  # the reference as the library holds it
+    # a few frames with markers that cannot be used: an unknown model (BAD_INPUT)
+    for f in (5, 6, 250):
+        frames[f].sizes[3:9, 2] = 7
+    frames[7].sizes[:, 2] = 7  # no usable marker at all
+    opts = sf.default_options(max_side=13, schedule=sf.SCHEDULE_MIXED, plan_hint=sf.PLAN_LATENCY)
+    srv = sf.Server(0, opts, device_mem_budget=64 << 20, max_frames=512, n_streams=streams)
+    window = 16
+    srv.track(ref, window)
+    offs = np.round(np.arange(len(frames)) / fps * 1e9).astype(np.uint64)
+    outs = srv.replay([(f.data, f.sizes, f.init, True) for f in frames], offs)
+    st = srv.stats()
+    # a tracked frame must hold one spot per marker
+    with pytest.raises(sf.SpotfitError):
+        srv.submit(frames[0].data[:13 * 13 * 31], frames[0].sizes[:31], frames[0].init[:31],
+                   track=True)
+    srv.close()
+    print("serve stats", st)
+    assert st["frames_done"] == len(frames) and st["frames_failed"] == 0
+    P = np.stack([o["params"] for o in outs])
+    S = np.stack([o["status"] for o in outs])
+    exp = oracle.drift_track(P, S, ref, window)
+    got = np.concatenate([o["drift"] for o in outs])
+    _drift_close(got["dx"], exp[:, 0])
+    _drift_close(got["dy"], exp[:, 1])
+    _drift_close(got["mean_dx"], exp[:, 2])
+    _drift_close(got["mean_dy"], exp[:, 3])
+    np.testing.assert_array_equal(got["n_used"], exp[:, 4].astype(np.int32))
+    np.testing.assert_array_equal(got["n_frames"], exp[:, 5].astype(np.int32))
+    assert got["n_used"][7] == 0 and 20 <= got["n_used"][5] <= 26 and got["n_frames"][7] > 0
+    # the tracked drift follows the true drift (window mean of the truth)
+    tw = np.stack([drift[max(0, f - window + 1):f + 1].mean(axis=0) for f in range(len(frames))])
+    err = np.stack([got["mean_dx"], got["mean_dy"]], axis=1) - tw
+    rms = np.sqrt(np.mean(err[window:] ** 2))
+    print(f"tracked drift rms error {rms:.4f} px")
+    assert rms < 0.01
