@@ -9,7 +9,9 @@ namespace lm {
 
 // What the next evaluation of a spot is: its start point, the first trial of
 // an iteration, or a retry with more damping.
-enum Mode : int { kNew = 0, kTrialFirst = 1, kTrialRetry = 2 };
+enum Mode : int { kNew = 0, kTrialFirst = 1, kTrialRetry = 2,
+                  // re-evaluations with a directly summed chi^2 before a close decision
+                  kRecheckBest = 3, kRecheckCand = 4 };
 
 __device__ __forceinline__ double clampn(double v, double lo, double hi) {
   return v < lo ? lo : (v > hi ? hi : v);

@@ -3,26 +3,28 @@
 //
 // The arithmetic is that of the separable kernel (f(r, c) = ex(c) * ey(r) for
 // Eq. 10 and its axis-aligned elliptical form, every sum of Eqs. 5-9 as
-// one-dimensional moments or bilinear forms, all in double precision, chi^2
-// summed directly over the pixels as Eq. 2 writes it).  What differs is the
-// mapping: a spot is held by a small group of L = 2, 4 or 8 lanes.
+// one-dimensional moments or bilinear forms, all in double precision).  What
+// differs is the mapping: a spot is held by a small group of L = 4, 8 or 16
+// lanes.
 //
 //  * Lane l of a group owns the columns c = l + L*j (j < CPL) with all their
-//    rows: the CPL*HM pixel values stay in registers (as float, exact for
-//    16-bit data) for the whole fit.  It computes ex(c) for its columns and
-//    ey(r) for the rows r = l + L*j; every lane then gathers all HM row
-//    factors from its group by DPP (or ds_swizzle) broadcasts.
-//  * The per-spot state (point, best point, normal equations, decisions) is
-//    kept in registers, identical on the L lanes: each lane takes every
-//    scalar step itself, so no LDS and no barriers are needed.
+//    rows: the CPL*HM raw pixel values stay in registers for the whole fit and
+//    are converted where used.  It computes ex(c) for its columns and ey(r)
+//    for the rows r = l + L*j; every lane then gathers all HM row factors from
+//    its group by DPP (or ds_swizzle) broadcasts.
+//  * The per-spot scalar state is identical on the L lanes: each lane takes
+//    every scalar step itself, and the iteration state lives in LDS, each lane
+//    reading back only its own writes, so no barriers are needed.
 //  * Group totals are log2(L) DPP butterfly steps; the two partners add the
 //    same two numbers, so every lane of a group holds bitwise the same total
 //    and takes the same branch.
 //
-// One trial evaluation costs per lane 2*CPL exponentials, ~7 double
-// operations per pixel it owns (two passes: the column sums t(c) = sum_r g ey
-// and row sums s(r) = sum_c g ex that give **G** and the derivative bilinear
-// forms; then the residual sum of squares), and a handful of group totals.
+// One trial evaluation costs per lane 2*CPL exponentials and one pass over
+// the pixels it owns: the column sums t(c) = sum_r g ey and the row sums
+// s(r) = sum_c g ex, which give **G** and the derivative bilinear forms.  For
+// 16-bit data chi^2 then follows from those sums and the exact per-spot
+// N sum g^2 - G^2 (Eq. 2 at the amplitudes of Eq. 6); float data takes a
+// second pass for the residual sum of squares.
 //
 // The Levenberg-Marquardt loop is the same flattened per-group state machine
 // as the wide kernel (Fit2DGaussian pseudo-code): every wave step evaluates
@@ -77,9 +79,20 @@ struct NState {
   double bv[4];   // right-hand side J^T (g - h) at best
   double best[4];  // point at the start of the iteration
   double chi_best, a_best, b_best;
+  double chib_err;  // error bound of chi_best (0: summed directly)
+  double cand[4];   // the candidate while the best point is re-evaluated
+  int mode_saved;   // the mode whose decision a re-evaluation completes
   // sums of the evaluation at pc that the derivative pass reuses
   double Sx, Sxx, Sy, Syy, FG, D, Bx, Bsx, By, Bsy;
 };
+
+// Bound on the gap between chi^2 from the closed form and chi^2 summed over
+// the pixels, in units of 2^-53 ((w + h) / 2 chi^2 + (2|a| (N FG + F G) +
+// a^2 (N FF + F^2)) / N): the first-order rounding of the closed form's terms
+// (the cancellations in N FG - F G and in D) plus the direct sum's own
+// (sqrt(N) <= (w + h) / 2).  The largest gap measured over every workload,
+// in double precision on the host, was 26 units.
+constexpr double kChiGapUnits = 256.0;
 
 // Pixel value of a stored 32-bit pattern: a 16-bit count, or a float.
 template <int DT>
@@ -114,6 +127,8 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
   double pc[4] = {0.0, 0.0, 0.0, 0.0};  // candidate point (accepted point after a decision)
   double a = 0.0, b = 0.0, chi = 0.0;   // Eq. 6 amplitudes and Eq. 2 error at pc
   double Gs = 0.0, Tme = 0.0;
+  double Vs = 0.0;       // 16-bit data: N sum g^2 - G^2 of the spot (exact)
+  double chi_err = 0.0;  // bound on |chi - chi summed over the pixels|
 #pragma unroll
   for (int j = 0; j < CPL; ++j) ex[j] = eyl[j] = 0.0;
   // Iteration state and the sums of the last evaluation, in LDS.  Every lane of
@@ -291,7 +306,8 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         double t[CPL];
 #pragma unroll
         for (int j = 0; j < CPL; ++j) t[j] = 0.0;
-        double gp = 0.0, byp = 0.0, bsyp = 0.0, gsum_px = 0.0;
+        double gp = 0.0, byp = 0.0, bsyp = 0.0, gsum_px = 0.0, ggp = 0.0;
+        uint32_t gsi = 0;
 #pragma unroll
         for (int r = 0; r < HM; ++r) {
           if (r < h) {
@@ -302,7 +318,12 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
               const double gd = pixel<DT>(g[j][r]);
               t[j] = __builtin_fma(gd, e, t[j]);
               sr = __builtin_fma(gd, ex[j], sr);
-              gsum_px += gd;
+              if constexpr (DT == SPOTFIT_U16) {
+                gsi += g[j][r];                 // sum g (integer)
+                ggp = __builtin_fma(gd, gd, ggp);  // sum g^2 (exact: integers below 2^53)
+              } else {
+                gsum_px += gd;
+              }
             }
             const double dyr = double(r) - y;
             const double es = e * sr;
@@ -319,7 +340,15 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
           bxp = __builtin_fma(dx, et, bxp);
           bsxp = __builtin_fma(dx * dx, et, bsxp);
         }
-        if (mode == kNew) Gs = gsum<L>(gsum_px);  // sum g of a new spot (exact for 16-bit data)
+        const double Nn = double(w * h);
+        if (mode == kNew) {  // per-spot constants of a new spot
+          if constexpr (DT == SPOTFIT_U16) {
+            Gs = double(gsum_i<L>((int)gsi));
+            Vs = Nn * gsum<L>(ggp) - Gs * Gs;  // every step exact
+          } else {
+            Gs = gsum<L>(gsum_px);
+          }
+        }
         const double Sx = gsum<L>(sxp), Sxx = gsum<L>(sxxp);
         const double Sy = gsum<L>(syp), Syy = gsum<L>(syyp);
         const double FG = gsum<L>(gp);
@@ -328,7 +357,6 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         S.By = gsum<L>(byp);
         S.Bsy = gsum<L>(bsyp);
         const double F = Sx * Sy, FF = Sxx * Syy;
-        const double Nn = double(w * h);
         const double D = Nn * FF - F * F;
         S.Sx = Sx;
         S.Sxx = Sxx;
@@ -340,41 +368,98 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         const double iD = rcp_nr(D);
         a = (Nn * FG - F * Gs) * iD;
         b = (Gs * FF - F * FG) * iD;
-        // residual sum of squares, r = alpha f + beta - g over the spot's pixels
-        double aex[CPL], bm[CPL], c2[CPL];
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-          aex[j] = a * ex[j];
-          bm[j] = li + L * j < w ? b : 0.0;
-          c2[j] = 0.0;
+        // direct sum over the pixels: always for float data; for 16-bit data
+        // only where a close decision is being re-taken
+        bool direct = DT != SPOTFIT_U16;
+        if constexpr (DT == SPOTFIT_U16) {
+          // Eq. 2 at the amplitudes of Eq. 6: with sum r = sum f r = 0 (Eq. 4),
+          // chi^2 = sum (g - mean g)^2 - a^2 sum (f - mean f)^2 = (V - a^2 D) / N,
+          // V = N sum g^2 - G^2 exact for 16-bit data; no second pixel pass.
+          // Bright spots cancel the most: up to 3e-11 of chi^2 measured.
+          const double c2 = (Vs - a * a * D) / Nn;
+          chi = c2 > 0.0 ? c2 : 0.0;
+          chi_err = kChiGapUnits * 0x1p-53 *
+                    (0.5 * double(w + h) * chi +
+                     (2.0 * fabs(a) * (Nn * FG + F * Gs) + a * a * (Nn * FF + F * F)) / Nn);
+          direct = mode == kRecheckBest || mode == kRecheckCand;
         }
+        if (__builtin_amdgcn_ballot_w64(direct) != 0 && direct) {
+          // the residual sum of squares, r = alpha f + beta - g
+          double aex[CPL], bm[CPL], c2[CPL];
 #pragma unroll
-        for (int r = 0; r < HM; ++r) {
-          if (r < h) {
-            const double e = ey[r];
+          for (int j = 0; j < CPL; ++j) {
+            aex[j] = a * ex[j];
+            bm[j] = li + L * j < w ? b : 0.0;
+            c2[j] = 0.0;
+          }
 #pragma unroll
-            for (int j = 0; j < CPL; ++j) {
-              // a fresh conversion: reusing the first pass's doubles would keep
-              // all CPL*HM of them live in registers
-              uint32_t gv = g[j][r];
-              asm("" : "+v"(gv));
-              const double res = __builtin_fma(aex[j], e, bm[j] - pixel<DT>(gv));
-              c2[j] = __builtin_fma(res, res, c2[j]);
+          for (int r = 0; r < HM; ++r) {
+            if (r < h) {
+              const double e = ey[r];
+#pragma unroll
+              for (int j = 0; j < CPL; ++j) {
+                // a fresh conversion: reusing the first pass's doubles would keep
+                // all CPL*HM of them live in registers
+                uint32_t gv = g[j][r];
+                asm("" : "+v"(gv));
+                const double res = __builtin_fma(aex[j], e, bm[j] - pixel<DT>(gv));
+                c2[j] = __builtin_fma(res, res, c2[j]);
+              }
             }
           }
-        }
-        double c2s = c2[0];
+          double c2s = c2[0];
 #pragma unroll
-        for (int j = 1; j < CPL; ++j) c2s += c2[j];
-        chi = gsum<L>(c2s);
+          for (int j = 1; j < CPL; ++j) c2s += c2[j];
+          chi = gsum<L>(c2s);
+          chi_err = 0.0;
+        }
         if (!okD || !__builtin_isfinite(chi) || !__builtin_isfinite(a) || !__builtin_isfinite(b))
           chi = __builtin_nan("");
       }
-      if (mode != kNew) ++n_trial;
+      if (mode == kTrialFirst || mode == kTrialRetry) ++n_trial;
 
       // ================= decisions (Fit2DGaussian loop) =================
       bool start = false, do_grad = false, do_solve = false, done = false, out_best = false;
-      if (mode == kNew) {
+      bool decide = true;
+      if (mode == kRecheckBest) {
+        // the best point's chi^2, summed directly; then the candidate's
+        S.chi_best = chi;
+        S.chib_err = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pc[q] = S.cand[q];
+        mode = kRecheckCand;
+        decide = false;
+      } else if (mode == kRecheckCand) {
+        mode = S.mode_saved;  // chi is now summed directly: take the decision
+      } else if (chi_err > 0.0) {
+        // a decision closer to its threshold than the closed form's error
+        // bound is re-taken with chi^2 summed directly (the best point's too
+        // when that comparison involves it), so that every decision is the
+        // one a direct sum takes
+        const double chib = S.chi_best, eb = S.chib_err;
+        bool near_self = fabs(chi - Tme) <= chi_err, near_best = false;
+        if (mode != kNew) {
+          const double e2 = chi_err + eb;
+          near_best = fabs(chi - chib * (1.0 - tau)) <= e2 || fabs(chi - chib * (1.0 + tau)) <= e2 ||
+                      fabs(chi - chib * (1.0 - o.min_delta)) <= e2;
+        }
+        if (near_self || near_best) {
+          S.mode_saved = mode;
+          if (near_best && eb > 0.0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              S.cand[q] = pc[q];
+              pc[q] = S.best[q];
+            }
+            mode = kRecheckBest;
+          } else {
+            mode = kRecheckCand;
+          }
+          decide = false;
+        }
+      }
+      if (!decide) {
+      } else if (mode == kNew) {
         start = true;
       } else {
         const double Chi = chi, chib = S.chi_best;
@@ -416,6 +501,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
             done = true;
           } else {
             S.chi_best = chi;
+            S.chib_err = chi_err;
             S.a_best = a;
             S.b_best = b;
 #pragma unroll

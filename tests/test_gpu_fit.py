@@ -71,6 +71,14 @@ def _sampled(gpu, cfg, side, n_sample, seed):
     r = oracle.fit_batch(sub, oracle.default_opts(), threads=8)
     gs = {k: v[idx] for k, v in g.items()}
     _check_strict(f"config {cfg} full size, {n_sample} sampled", gs, r)
+    # every spot: the oracle's stop reason and iteration count, except where the
+    # oracle's own decision margin is inside the knife-edge band
+    full = oracle.fit_batch(b, oracle.default_opts(), threads=16)
+    diff = (g["status"] != full["status"]) | (g["iters"] != full["iters"])
+    knife = (full["margin_chi"] < CHI_BAND) | (full["margin_step"] < STEP_BAND)
+    print(f"config {cfg}: {int(diff.sum())} of {b.n} spots stop differently, "
+          f"{int((diff & ~knife).sum())} outside the knife-edge band")
+    assert int((diff & ~knife).sum()) == 0
     return b, g
 
 
