@@ -262,6 +262,42 @@ int spotfit_autotune(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                      spotfit_tune_report_t* report, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Captured fits of fixed-shape batches (HIP graphs).                        */
+/* ------------------------------------------------------------------------ */
+typedef struct spotfit_graph spotfit_graph_t; /* opaque */
+
+/* Optional host side of a captured fit; every pointer is PINNED host memory
+ * (hipHostMalloc) or NULL (that copy is left out of the graph). */
+typedef struct {
+  const void* data;        /* data_bytes bytes copied to the device `data` first   */
+  int64_t data_bytes;
+  const float* init;       /* n x 4 start values copied to the device `init` first */
+  float* params;           /* results copied back after the fit: n x 6             */
+  float* chi2;             /* n                                                     */
+  int32_t* iters;          /* n                                                     */
+  int32_t* status;         /* n                                                     */
+} spotfit_graph_io_t;
+
+/* Record one fit of a fixed batch (arguments as spotfit_fit_spots: device
+ * arrays, host opt) into a HIP graph, with the host copies `io` names before
+ * and after it (io may be NULL), for camera frames whose spot shapes stay the
+ * same from frame to frame: the caller refills the inputs (device arrays, or
+ * the pinned host buffers of io) and replays the whole call with one
+ * spotfit_graph_launch.  The capture runs on a private stream and launches
+ * nothing; the mixed schedule's workspace is reserved beforehand.  Replays use
+ * the context's buffers: do not overlap them with other calls on the same
+ * context.  n_spots must be > 0.  Returns SPOTFIT_OK or a negative
+ * spotfit_error_t. */
+int spotfit_graph_create(spotfit_graph_t** g, spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                         const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
+                         int64_t n_spots, const spotfit_options_t* opt, float* params_out,
+                         float* chi2_out, int32_t* iters_out, int32_t* status_out,
+                         const spotfit_graph_io_t* io);
+/* Replay the captured call on `stream` (results valid after a stream sync). */
+int spotfit_graph_launch(spotfit_graph_t* g, void* stream);
+void spotfit_graph_destroy(spotfit_graph_t* g);
+
+/* ------------------------------------------------------------------------ */
 /* Serving loop for camera frames (real-time tracking of fiducial spots).    */
 /* ------------------------------------------------------------------------ */
 typedef struct spotfit_serve spotfit_serve_t; /* opaque */

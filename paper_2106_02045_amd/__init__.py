@@ -28,7 +28,8 @@ EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_
             "spotfit_serve_submit", "spotfit_serve_poll", "spotfit_serve_wait",
             "spotfit_serve_stats", "spotfit_serve_destroy", "spotfit_serve_replay",
             "spotfit_serve_last_error", "spotfit_get_stats", "spotfit_autotune",
-            "spotfit_moment_init", "spotfit_peak_init", "spotfit_serve_track"]
+            "spotfit_moment_init", "spotfit_peak_init", "spotfit_serve_track",
+            "spotfit_graph_create", "spotfit_graph_launch", "spotfit_graph_destroy"]
 E_AGAIN = -6
 
 
@@ -53,6 +54,19 @@ class Options(ctypes.Structure):
         ("max_side", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
         ("plan_hint", ctypes.c_int32),
+    ]
+
+
+class GraphIO(ctypes.Structure):
+    """Mirror of spotfit_graph_io_t (pinned host pointers or NULL)."""
+    _fields_ = [
+        ("data", ctypes.c_void_p),
+        ("data_bytes", ctypes.c_int64),
+        ("init", ctypes.c_void_p),
+        ("params", ctypes.c_void_p),
+        ("chi2", ctypes.c_void_p),
+        ("iters", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
     ]
 
 
@@ -169,6 +183,14 @@ def lib():
         L.spotfit_serve_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
         L.spotfit_serve_track.argtypes = [vp, i32, vp, i32]
         L.spotfit_serve_track.restype = ctypes.c_int
+        L.spotfit_graph_create.argtypes = [ctypes.POINTER(vp), vp, vp, i32, vp, vp, vp, i64,
+                                           ctypes.POINTER(Options), vp, vp, vp, vp,
+                                           ctypes.POINTER(GraphIO)]
+        L.spotfit_graph_create.restype = ctypes.c_int
+        L.spotfit_graph_launch.argtypes = [vp, vp]
+        L.spotfit_graph_launch.restype = ctypes.c_int
+        L.spotfit_graph_destroy.argtypes = [vp]
+        L.spotfit_graph_destroy.restype = None
         L.spotfit_serve_stats.restype = ctypes.c_int
         L.spotfit_serve_destroy.argtypes = [vp]
         L.spotfit_serve_destroy.restype = None
@@ -271,6 +293,20 @@ class Context:
                        status=torch.empty(n, dtype=torch.int32, device=dev))
             if want_evals:
                 out["evals"] = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        else:
+            want = dict(params=((n, 6), torch.float32), chi2=((n,), torch.float32),
+                        iters=((n,), torch.int32), status=((n,), torch.int32),
+                        evals=((n, 2), torch.int32))
+            for k, (shape, dtype) in want.items():
+                if k not in out:
+                    if k == "evals":
+                        continue
+                    raise ValueError(f"out is missing {k}")
+                t = out[k]
+                if (tuple(t.shape) != shape or t.dtype != dtype or not t.is_contiguous()
+                        or t.device != dev):
+                    raise TypeError(f"out[{k!r}] must be a contiguous {dtype} tensor of shape "
+                                    f"{shape} on {dev}")
         return n, dt, out
 
     def fit_spots(self, data, sizes, offsets, init, opts: Optional[Options] = None,
@@ -293,6 +329,44 @@ class Context:
                                 st.cuda_stream)
         _check(rc, "spotfit_fit_spots")
         return out
+
+    def graph(self, data, sizes, offsets, init, opts: Optional[Options] = None, out=None,
+              host=None):
+        """Capture one fit of this fixed batch into a HIP graph (spotfit_graph_create).
+
+        The device tensors (and `out`, allocated if None) are baked into the graph: refill
+        them between launches.  host: optional dict of PINNED CPU tensors with keys
+        data, init (copied to the device before the fit) and params, chi2, iters, status
+        (copied back after it).  Returns a Graph whose launch() replays the whole call."""
+        n, dt, out = self._marshal(data, sizes, offsets, init, out, False)
+        io = None
+        host = dict(host or {})
+        if host:
+            for k, t in host.items():
+                if k not in ("data", "init", "params", "chi2", "iters", "status"):
+                    raise KeyError(k)
+                if t.is_cuda or not t.is_pinned() or not t.is_contiguous():
+                    raise TypeError(f"host[{k!r}] must be a contiguous pinned CPU tensor")
+            for k in ("init", "params", "chi2", "iters", "status"):
+                ref = init if k == "init" else out[k]
+                if k in host and (host[k].shape != ref.shape or host[k].dtype != ref.dtype):
+                    raise ValueError(f"host[{k!r}] must match {tuple(ref.shape)} {ref.dtype}")
+            if "data" in host and (host["data"].dtype != data.dtype
+                                   or host["data"].numel() != data.numel()):
+                raise ValueError("host['data'] must match the device data")
+            ptr = lambda k: host[k].data_ptr() if k in host else None
+            io = GraphIO(ptr("data"), host["data"].numel() * host["data"].element_size()
+                         if "data" in host else 0, ptr("init"), ptr("params"), ptr("chi2"),
+                         ptr("iters"), ptr("status"))
+        h = ctypes.c_void_p()
+        rc = lib().spotfit_graph_create(ctypes.byref(h), self._h, data.data_ptr(), dt,
+                                        sizes.data_ptr(), offsets.data_ptr(), init.data_ptr(), n,
+                                        ctypes.byref(opts) if opts is not None else None,
+                                        out["params"].data_ptr(), out["chi2"].data_ptr(),
+                                        out["iters"].data_ptr(), out["status"].data_ptr(),
+                                        ctypes.byref(io) if io is not None else None)
+        _check(rc, "spotfit_graph_create")
+        return Graph(h, keep=(data, sizes, offsets, init, out, host, io), out=out)
 
     def autotune(self, data, sizes, offsets, init, opts: Optional[Options] = None, reps: int = 3,
                  out=None, stream=None):
@@ -365,6 +439,31 @@ class Context:
         return dict(n_spots=res.n_spots, status_count=list(res.status_count),
                     iters_hist=list(res.iters_hist), grad_evals=res.grad_evals,
                     trial_evals=res.trial_evals)
+
+
+class Graph:
+    """A captured fit (spotfit_graph_t); holds the tensors baked into it."""
+
+    def __init__(self, h, keep, out):
+        self._h = h
+        self._keep = keep
+        self.out = out
+
+    def launch(self, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.out["params"].device)
+        _check(lib().spotfit_graph_launch(self._h, st.cuda_stream), "spotfit_graph_launch")
+
+    def close(self):
+        if self._h:
+            lib().spotfit_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> int:

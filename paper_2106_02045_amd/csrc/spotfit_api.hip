@@ -564,3 +564,96 @@ const char* spotfit_last_error(void) { return g_last_error.c_str(); }
 int spotfit_version(void) { return 100; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Captured fits of fixed-shape batches: the copies and kernels of one call,
+// recorded once into a HIP graph on a private stream and replayed with one
+// launch.
+// ---------------------------------------------------------------------------
+struct spotfit_graph {
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int spotfit_graph_create(spotfit_graph_t** out, spotfit_ctx_t* ctx, const void* data,
+                         int32_t dtype, const spotfit_shape_t* sizes, const int64_t* offsets,
+                         const float* init, int64_t n, const spotfit_options_t* opt,
+                         float* params_out, float* chi2_out, int32_t* iters_out,
+                         int32_t* status_out, const spotfit_graph_io_t* io) {
+  if (!out) return fail(SPOTFIT_E_NULL, "graph_create: NULL out pointer");
+  *out = nullptr;
+  spotfit_options_t o;
+  int rc = check_call(ctx, data, dtype, sizes, offsets, init, n, opt, params_out, chi2_out,
+                      iters_out, status_out, &o, "graph_create");
+  if (rc != SPOTFIT_OK) return rc;
+  if (n == 0) return fail(SPOTFIT_E_ARG, "graph_create: n_spots = 0");
+  if (io && io->data && io->data_bytes <= 0)
+    return fail(SPOTFIT_E_ARG, "graph_create: io->data_bytes must be > 0 with io->data");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+  // the mixed schedule's workspace is sized before the capture: nothing allocates inside it
+  if (o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED && n > ctx->ws_cap) {
+    rc = spotfit_ctx_reserve(ctx, n);
+    if (rc != SPOTFIT_OK) return rc;
+  }
+  spotfit_graph* g = new (std::nothrow) spotfit_graph();
+  if (!g) return fail(SPOTFIT_E_ARG, "graph_create: out of host memory");
+  g->device = ctx->device;
+  hipStream_t st = nullptr;
+  e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return fail_hip(e, "hipStreamCreateWithFlags");
+  }
+  e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess && io && io->data)
+    e = hipMemcpyAsync(const_cast<void*>(data), io->data, (size_t)io->data_bytes,
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && io && io->init)
+    e = hipMemcpyAsync(const_cast<float*>(init), io->init, sizeof(float) * 4 * (size_t)n,
+                       hipMemcpyHostToDevice, st);
+  rc = SPOTFIT_OK;
+  if (e == hipSuccess)
+    rc = launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
+                    status_out, nullptr, st);
+  if (e == hipSuccess && rc == SPOTFIT_OK && io && io->params)
+    e = hipMemcpyAsync(io->params, params_out, sizeof(float) * 6 * (size_t)n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && rc == SPOTFIT_OK && io && io->chi2)
+    e = hipMemcpyAsync(io->chi2, chi2_out, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && rc == SPOTFIT_OK && io && io->iters)
+    e = hipMemcpyAsync(io->iters, iters_out, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && rc == SPOTFIT_OK && io && io->status)
+    e = hipMemcpyAsync(io->status, status_out, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, st);
+  // always end the capture, so the stream leaves capture mode whatever failed
+  const hipError_t e_end = hipStreamEndCapture(st, &g->graph);
+  if (e == hipSuccess) e = e_end;
+  if (e == hipSuccess && rc == SPOTFIT_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(st);
+  if (e != hipSuccess || rc != SPOTFIT_OK) {
+    const std::string why = rc != SPOTFIT_OK ? std::string(spotfit_last_error()) : hipGetErrorString(e);
+    spotfit_graph_destroy(g);
+    return rc != SPOTFIT_OK ? fail(rc, "graph_create: " + why) : fail_hip(e, "graph_create");
+  }
+  *out = g;
+  return SPOTFIT_OK;
+}
+
+int spotfit_graph_launch(spotfit_graph_t* g, void* stream) {
+  if (!g || !g->exec) return fail(SPOTFIT_E_NULL, "graph_launch: NULL graph");
+  const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+  return SPOTFIT_OK;
+}
+
+void spotfit_graph_destroy(spotfit_graph_t* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+}  // extern "C"

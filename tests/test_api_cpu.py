@@ -126,7 +126,9 @@ def test_stats_and_autotune_argument_errors():
 def test_stats_and_report_struct_layout_matches_header():
     import subprocess
     import tempfile
-    checks = [("spotfit_stats_t", sf.Stats), ("spotfit_tune_report_t", sf.TuneReport)]
+    checks = [("spotfit_stats_t", sf.Stats), ("spotfit_tune_report_t", sf.TuneReport),
+              ("spotfit_frame_t", sf.Frame), ("spotfit_drift_t", sf.Drift),
+              ("spotfit_graph_io_t", sf.GraphIO), ("spotfit_serve_stats_t", sf.ServeStats)]
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "p.c")
         body = ""
@@ -149,3 +151,16 @@ def test_stats_and_report_struct_layout_matches_header():
 
 def test_version():
     assert sf.version() >= 100
+
+
+def test_graph_and_tracking_argument_errors():
+    # host-side checks only: no HIP call is reached
+    L = sf.lib()
+    h = ctypes.c_void_p()
+    assert L.spotfit_graph_create(None, None, 1, 0, 1, 1, 1, 10, None, 1, 1, 1, 1, None) == -1
+    assert L.spotfit_graph_create(ctypes.byref(h), None, 1, 0, 1, 1, 1, 10, None, 1, 1, 1, 1,
+                                  None) == -1
+    assert h.value is None
+    assert L.spotfit_graph_launch(None, None) == -1
+    L.spotfit_graph_destroy(None)
+    assert L.spotfit_serve_track(None, 4, None, 8) == -1
