@@ -281,6 +281,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
       }
       advance();
       took = true;
+      if (s >= 0) load_pixels();
     } else if (s >= 0) {
       // ================= trial evaluation at pc (Eqs. 2, 5, 6, 10) =================
       {
@@ -376,11 +377,12 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
           // chi^2 = sum (g - mean g)^2 - a^2 sum (f - mean f)^2 = (V - a^2 D) / N,
           // V = N sum g^2 - G^2 exact for 16-bit data; no second pixel pass.
           // Bright spots cancel the most: up to 3e-11 of chi^2 measured.
-          const double c2 = (Vs - a * a * D) / Nn;
+          const double iNn = rcp_nr(Nn);
+          const double c2 = (Vs - a * a * D) * iNn;
           chi = c2 > 0.0 ? c2 : 0.0;
           chi_err = kChiGapUnits * 0x1p-53 *
                     (0.5 * double(w + h) * chi +
-                     (2.0 * fabs(a) * (Nn * FG + F * Gs) + a * a * (Nn * FF + F * F)) / Nn);
+                     (2.0 * fabs(a) * (Nn * FG + F * Gs) + a * a * (Nn * FF + F * F)) * iNn);
           direct = mode == kRecheckBest || mode == kRecheckCand;
         }
         if (__builtin_amdgcn_ballot_w64(direct) != 0 && direct) {
@@ -545,6 +547,10 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         took = true;
       }
 
+      // pixels for the next step's evaluation (the next spot's after a take), issued
+      // before the derivative pass and the solve so that those cover their latency
+      if (s >= 0) load_pixels();
+
       // ================= derivative pass at pc (Eqs. 7-9, 11) =================
       if (do_grad) {
         const double x = pc[0], y = pc[1];
@@ -648,8 +654,6 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
       }
 
     }
-    // pixels for the next step's evaluation (the next spot's after a take)
-    if (s >= 0) load_pixels();
     reserve(took);
   }
 }
