@@ -592,7 +592,15 @@ int spotfit_graph_create(spotfit_graph_t** out, spotfit_ctx_t* ctx, const void* 
   if (n == 0) return fail(SPOTFIT_E_ARG, "graph_create: n_spots = 0");
   if (io && io->data && io->data_bytes <= 0)
     return fail(SPOTFIT_E_ARG, "graph_create: io->data_bytes must be > 0 with io->data");
-  hipError_t e = hipSetDevice(ctx->device);
+  // the caller's current device is restored on return
+  struct DeviceGuard {
+    int prev = -1;
+    ~DeviceGuard() {
+      if (prev >= 0) (void)hipSetDevice(prev);
+    }
+  } guard;
+  hipError_t e = hipGetDevice(&guard.prev);
+  if (e == hipSuccess) e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
   // the mixed schedule's workspace is sized before the capture: nothing allocates inside it
   if (o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED && n > ctx->ws_cap) {

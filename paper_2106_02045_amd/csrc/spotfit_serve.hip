@@ -410,6 +410,14 @@ int spotfit_serve_track(spotfit_serve_t* sv, int32_t n_markers, const float* ref
   std::lock_guard<std::mutex> lk(sv->mu);
   for (uint64_t t = sv->oldest_ticket; t < sv->next_ticket; ++t)  // frames in flight
     if (sv->rec(t).state != kDone && sv->rec(t).state != kFailed) return SPOTFIT_E_AGAIN;
+  // the caller's current device is restored on return
+  struct Restore {
+    int dev = -1;
+    ~Restore() {
+      if (dev >= 0) (void)hipSetDevice(dev);
+    }
+  } restore;
+  (void)hipGetDevice(&restore.dev);
   (void)hipSetDevice(sv->device);
   sv->free_tracking();
   sv->track_next = 0;
