@@ -326,11 +326,12 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
                 gsum_px += gd;
               }
             }
-            const double dyr = double(r) - y;
+            // moments about row 0 (r and r^2 are constants of the unrolled
+            // loop); shifted to the spot's centre after the group totals
             const double es = e * sr;
             gp += es;
-            byp = __builtin_fma(dyr, es, byp);
-            bsyp = __builtin_fma(dyr * dyr, es, bsyp);
+            byp = __builtin_fma(double(r), es, byp);
+            bsyp = __builtin_fma(double(r * r), es, bsyp);
           }
         }
         double bxp = 0.0, bsxp = 0.0;
@@ -355,8 +356,11 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         const double FG = gsum<L>(gp);
         S.Bx = gsum<L>(bxp);
         S.Bsx = gsum<L>(bsxp);
-        S.By = gsum<L>(byp);
-        S.Bsy = gsum<L>(bsyp);
+        {
+          const double R1 = gsum<L>(byp), R2 = gsum<L>(bsyp);  // sum r e s(r), sum r^2 e s(r)
+          S.By = __builtin_fma(-y, FG, R1);                       // sum (r - y) e s(r)
+          S.Bsy = __builtin_fma(-y, __builtin_fma(2.0, R1, -y * FG), R2);  // sum (r - y)^2 e s(r)
+        }
         const double F = Sx * Sy, FF = Sxx * Syy;
         const double D = Nn * FF - F * F;
         S.Sx = Sx;
