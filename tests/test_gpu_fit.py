@@ -296,3 +296,19 @@ def test_autotune_keeps_a_plan_and_stays_exact(schedule):
     torch.cuda.synchronize()
     for k in ("params", "chi2", "iters", "status"):
         np.testing.assert_array_equal(again[k].cpu().numpy(), g[k])
+
+
+def test_single_pass_chi2_takes_the_direct_sums_decisions(gpu):
+    # 16-bit data: chi^2 from the pixel pass's sums, close decisions re-taken with
+    # the direct sum; float data holding the same integers: chi^2 always summed
+    # directly.  Every stop reason and iteration count must agree.
+    b = spotgen.config(1, n=200000, threads=16)
+    g16 = gpu(b, max_side=16)
+    f32 = spotgen.SpotBatch(b.data.astype(np.float32), b.sizes, b.offsets, b.init, b.truth, "f32")
+    g32 = gpu(f32, max_side=16)
+    np.testing.assert_array_equal(g16["status"], g32["status"])
+    np.testing.assert_array_equal(g16["iters"], g32["iters"])
+    np.testing.assert_array_equal(g16["evals"], g32["evals"])
+    rel = np.abs(g16["chi2"].astype(np.float64) - g32["chi2"]) / np.maximum(g32["chi2"], 1e-6)
+    assert rel.max() < 1e-6
+    assert np.abs(g16["params"][:, :2] - g32["params"][:, :2]).max() < 1e-6
