@@ -17,9 +17,10 @@
 //
 // Mapping: a group of L lanes per spot, lane l owning the columns l + L*j as in
 // the fit kernel; groups step over the spots with a grid stride.  The ring
-// median is a radix select over order-preserving 32-bit keys of the ring values
-// (each lane holds every L-th ring pixel; one group count per key bit), so no
-// sort and no LDS are needed.
+// median is a radix select, two bits per round, over the 16-bit values (or
+// order-preserving 32-bit keys of float values) of the ring pixels, each lane
+// holding every L-th of them, so no sort and no LDS are needed; the moments are
+// summed in one pass about the ROI centre.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,7 +65,7 @@ __device__ __forceinline__ void moment_init_spot(const void* data, int dtype, co
                                                  int64_t off, int li, float* o4);
 
 template <int L, int CPL>
-__global__ __launch_bounds__(64) void moment_init_kernel(const void* data, int dtype,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void moment_init_kernel(const void* data, int dtype,
                                                          const spotfit_shape_t* sizes,
                                                          const int64_t* offsets, int64_t n,
                                                          int max_side, int max_pixels,
@@ -86,6 +87,30 @@ __global__ __launch_bounds__(64) void moment_init_kernel(const void* data, int d
   }
 }
 
+// The k-th smallest of the group's keys (each lane holds RM of them; keys of
+// empty slots are all ones): a radix select, two bits per round from the top of
+// BITS-bit keys.  Each round counts, over the group, the keys below the three
+// candidates prefix|01, prefix|10, prefix|11 (the three counts, at most 124
+// each, travel packed in one integer through a single group total) and keeps
+// the largest candidate with at most k keys below it.
+template <int L, int RM, int BITS>
+__device__ __forceinline__ uint32_t select_kth(const uint32_t (&key)[RM], int k) {
+  uint32_t v = 0;
+#pragma unroll
+  for (int shift = BITS - 2; shift >= 0; shift -= 2) {
+    const uint32_t c1 = v | (1u << shift), c2 = v | (2u << shift), c3 = v | (3u << shift);
+    int cnt = 0;
+#pragma unroll
+    for (int m = 0; m < RM; ++m)
+      cnt += (key[m] < c1 ? 1 : 0) + (key[m] < c2 ? 0x100 : 0) + (key[m] < c3 ? 0x10000 : 0);
+    cnt = gsum_i<L>(cnt);
+    const uint32_t d = ((cnt & 0xff) <= k ? 1u : 0u) + (((cnt >> 8) & 0xff) <= k ? 1u : 0u) +
+                       (((cnt >> 16) & 0xff) <= k ? 1u : 0u);
+    v |= d << shift;
+  }
+  return v;
+}
+
 template <int L, int CPL>
 __device__ __forceinline__ void moment_init_spot(const void* data, int dtype, const spotfit_shape_t sh,
                                                  int64_t off, int li, float* o4) {
@@ -94,6 +119,8 @@ __device__ __forceinline__ void moment_init_spot(const void* data, int dtype, co
   const int w = sh.w, h = sh.h;
 
   // ---- background: median of the border ring ----
+  // keys: the 16-bit values themselves, or order-preserving 32-bit keys of floats
+  const bool u16 = dtype == SPOTFIT_U16;
   const int nr = 2 * (w + h - 2);
   uint32_t key[RM];
 #pragma unroll
@@ -112,19 +139,14 @@ __device__ __forceinline__ void moment_init_spot(const void* data, int dtype, co
       r = q - 2 * w - (h - 2) + 1;
       c = w - 1;
     }
-    key[m] = key_of(load_px(data, dtype, off + r * w + c));
+    const int64_t i = off + r * w + c;
+    key[m] = u16 ? uint32_t(static_cast<const uint16_t*>(data)[i])
+                 : key_of(static_cast<const float*>(data)[i]);
   }
 #pragma unroll
   for (int m = 0; m < RM; ++m) key[m] = li + L * m < nr ? key[m] : 0xFFFFFFFFu;
   const int k1 = nr / 2 - 1;  // the two middle order statistics: k1 and k1 + 1
-  uint32_t v1 = 0;
-  for (int bit = 31; bit >= 0; --bit) {
-    const uint32_t cand = v1 | (1u << bit);
-    int cnt = 0;
-#pragma unroll
-    for (int m = 0; m < RM; ++m) cnt += key[m] < cand ? 1 : 0;
-    if (gsum_i<L>(cnt) <= k1) v1 = cand;
-  }
+  const uint32_t v1 = u16 ? select_kth<L, RM, 16>(key, k1) : select_kth<L, RM, 32>(key, k1);
   int le = 0;
   uint32_t above = 0xFFFFFFFFu;
 #pragma unroll
@@ -135,54 +157,50 @@ __device__ __forceinline__ void moment_init_spot(const void* data, int dtype, co
   le = gsum_i<L>(le);
   above = gmin_u<L>(above);
   const uint32_t v2 = le >= k1 + 2 ? v1 : above;
-  const double b0 = 0.5 * (double(value_of(v1)) + double(value_of(v2)));
+  const double b0 = u16 ? 0.5 * (double(v1) + double(v2))
+                        : 0.5 * (double(value_of(v1)) + double(value_of(v2)));
 
-  // ---- weights, centroid, second moments ----
-  // every slot loaded at once (clamped into the spot), masked afterwards
-  float gv[CPL][HM];
-#pragma unroll
-  for (int j = 0; j < CPL; ++j) {
-    const int c = li + L * j < w ? li + L * j : w - 1;
-#pragma unroll
-    for (int r = 0; r < HM; ++r) gv[j][r] = load_px(data, dtype, off + (r < h ? r : h - 1) * w + c);
-  }
-  double wt[CPL][HM];
-  double sw = 0.0, swx = 0.0, swy = 0.0;
+  // ---- weights, centroid, second moments (one pass, about the ROI centre) ----
+  // column by column: every slot of a column loaded at once (clamped into the
+  // spot), masked afterwards
+  const double c0 = 0.5 * (w - 1), r0 = 0.5 * (h - 1);
+  double sw = 0.0, swx = 0.0, swy = 0.0, swxx = 0.0, swyy = 0.0;
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
     const int c = li + L * j;
+    const int cc = c < w ? c : w - 1;
+    float gv[HM];
+#pragma unroll
+    for (int r = 0; r < HM; ++r) gv[r] = load_px(data, dtype, off + (r < h ? r : h - 1) * w + cc);
+    const double dx = double(c) - c0;
+    double cw = 0.0, cwy = 0.0, cwyy = 0.0;  // this column's sums
 #pragma unroll
     for (int r = 0; r < HM; ++r) {
-      const double v = (c < w && r < h) ? fmax(double(gv[j][r]) - b0, 0.0) : 0.0;
-      wt[j][r] = v;
-      sw += v;
-      swx = __builtin_fma(v, double(c), swx);
-      swy = __builtin_fma(v, double(r), swy);
+      const double v = (c < w && r < h) ? fmax(double(gv[r]) - b0, 0.0) : 0.0;
+      const double dy = double(r) - r0;
+      cw += v;
+      cwy = __builtin_fma(v, dy, cwy);
+      cwyy = __builtin_fma(v * dy, dy, cwyy);
     }
+    sw += cw;
+    swx = __builtin_fma(cw, dx, swx);
+    swxx = __builtin_fma(cw * dx, dx, swxx);
+    swy += cwy;
+    swyy += cwyy;
   }
   sw = gsum<L>(sw);
   swx = gsum<L>(swx);
   swy = gsum<L>(swy);
+  swxx = gsum<L>(swxx);
+  swyy = gsum<L>(swyy);
   double o[4];
   if (!(sw > 0.0)) {
     o[0] = 0.5 * (w - 1);
     o[1] = 0.5 * (h - 1);
     o[2] = o[3] = 1.5;
   } else {
-    const double cx = swx / sw, cy = swy / sw;
-    double vx = 0.0, vy = 0.0;
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const double dx = double(li + L * j) - cx;
-#pragma unroll
-      for (int r = 0; r < HM; ++r) {
-        const double dy = double(r) - cy;
-        vx = __builtin_fma(wt[j][r] * dx, dx, vx);
-        vy = __builtin_fma(wt[j][r] * dy, dy, vy);
-      }
-    }
-    vx = gsum<L>(vx) / sw;
-    vy = gsum<L>(vy) / sw;
+    const double mx = swx / sw, my = swy / sw;  // centroid relative to the ROI centre
+    const double vx = swxx / sw - mx * mx, vy = swyy / sw - my * my;
     double sx, sy;
     if (sh.model == SPOTFIT_SYM) {
       sx = sy = sqrt(0.5 * (vx + vy));
@@ -191,8 +209,8 @@ __device__ __forceinline__ void moment_init_spot(const void* data, int dtype, co
       sy = sqrt(vy);
     }
     const double lo = 0.8, hi = 0.25 * double(w > h ? w : h);
-    o[0] = cx;
-    o[1] = cy;
+    o[0] = c0 + mx;
+    o[1] = r0 + my;
     o[2] = sx < lo ? lo : (sx > hi ? hi : sx);
     o[3] = sy < lo ? lo : (sy > hi ? hi : sy);
   }
