@@ -65,7 +65,7 @@ __device__ __forceinline__ void moment_init_spot(const void* data, int dtype, co
                                                  int64_t off, int li, float* o4);
 
 template <int L, int CPL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void moment_init_kernel(const void* data, int dtype,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void moment_init_kernel(const void* data, int dtype,
                                                          const spotfit_shape_t* sizes,
                                                          const int64_t* offsets, int64_t n,
                                                          int max_side, int max_pixels,
@@ -161,22 +161,18 @@ __device__ __forceinline__ void moment_init_spot(const void* data, int dtype, co
                         : 0.5 * (double(value_of(v1)) + double(value_of(v2)));
 
   // ---- weights, centroid, second moments (one pass, about the ROI centre) ----
-  // column by column: every slot of a column loaded at once (clamped into the
-  // spot), masked afterwards
+  // column by column, rows streamed
   const double c0 = 0.5 * (w - 1), r0 = 0.5 * (h - 1);
   double sw = 0.0, swx = 0.0, swy = 0.0, swxx = 0.0, swyy = 0.0;
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
     const int c = li + L * j;
-    const int cc = c < w ? c : w - 1;
-    float gv[HM];
-#pragma unroll
-    for (int r = 0; r < HM; ++r) gv[r] = load_px(data, dtype, off + (r < h ? r : h - 1) * w + cc);
+    if (c >= w) continue;
     const double dx = double(c) - c0;
     double cw = 0.0, cwy = 0.0, cwyy = 0.0;  // this column's sums
-#pragma unroll
-    for (int r = 0; r < HM; ++r) {
-      const double v = (c < w && r < h) ? fmax(double(gv[r]) - b0, 0.0) : 0.0;
+#pragma unroll 4
+    for (int r = 0; r < h; ++r) {
+      const double v = fmax(double(load_px(data, dtype, off + r * w + c)) - b0, 0.0);
       const double dy = double(r) - r0;
       cw += v;
       cwy = __builtin_fma(v, dy, cwy);
@@ -255,8 +251,99 @@ __device__ __forceinline__ float gmax_f(float v) {
 constexpr double kExpMinusHalf = 0x1.368b2fc6f960ap-1;  // e^(-1/2), correctly rounded
 constexpr double kPi = 0x1.921fb54442d18p+1;
 
+// Zeros that the loads of a neighbour column outside the spot read instead
+// (row offsets of a 32 x 32 spot at most).  Never written; not const, so that
+// its pointer and the pixel pointer stay in the global address space.
+__device__ uint16_t kZeroCol[32 * 32];
+
+// One butterfly step of the best-window selection: keep the partner's window
+// when its mean is larger, or equal with a smaller index.  Both partners see
+// the same two windows, so they keep the same one.
+template <int CTRL>
+__device__ __forceinline__ void best_step(int& bacc, int& bcnt, int& bk) {
+  const int pa = dpp_i<CTRL>(bacc), pc = dpp_i<CTRL>(bcnt), pk = dpp_i<CTRL>(bk);
+  const int lhs = pa * bcnt, rhs = bacc * pc;
+  if (lhs > rhs || (lhs == rhs && pk < bk)) {
+    bacc = pa;
+    bcnt = pc;
+    bk = pk;
+  }
+}
+
+// 16-bit pixels: the same recipe in integer arithmetic.  A window's sum is an
+// integer and its pixel count 4, 6 or 9, so two means compare exactly by cross
+// multiplication; for such sums (below 2^20) two different means also differ
+// by far more than a double's rounding, so this ordering (and its ties) is the
+// one the correctly rounded mean / count quotients give.
 template <int L, int CPL>
-__global__ __launch_bounds__(64) void peak_init_kernel(const void* data, int dtype,
+__device__ __forceinline__ void peak_init_u16(const uint16_t* px, int w, int h, int li, float* o4) {
+  int bacc = -1, bcnt = 1, bk = 0x7fffffff;  // best window: sum, pixel count, row-major index
+  int lo = 0x7fffffff, hi = -1;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int c = li + L * j;
+    if (c >= w) continue;
+    const uint16_t* cm = c >= 1 ? px + (c - 1) : kZeroCol;
+    const uint16_t* cc = px + c;
+    const uint16_t* cp = c + 1 < w ? px + (c + 1) : kZeroCol;
+    const int ncol = (c >= 1 ? 1 : 0) + 1 + (c + 1 < w ? 1 : 0);
+    // rows streamed top to bottom: row sums of the three columns for r - 1, r, r + 1
+    int hp = 0;
+    int hc = int(cm[0]) + int(cc[0]) + int(cp[0]);
+    int gc = int(cc[0]);
+#pragma unroll 2
+    for (int r = 0; r < h; ++r) {
+      int hn = 0, gn = 0;
+      if (r + 1 < h) {
+        const int ro = (r + 1) * w;
+        gn = int(cc[ro]);
+        hn = int(cm[ro]) + gn + int(cp[ro]);
+      }
+      lo = gc < lo ? gc : lo;
+      hi = gc > hi ? gc : hi;
+      const int acc = hp + hc + hn;
+      const int cnt = ncol * ((r >= 1 ? 1 : 0) + 1 + (r + 1 < h ? 1 : 0));
+      const int k = r * w + c;
+      const int lhs = acc * bcnt, rhs = bacc * cnt;
+      if (lhs > rhs || (lhs == rhs && k < bk)) {
+        bacc = acc;
+        bcnt = cnt;
+        bk = k;
+      }
+      hp = hc;
+      hc = hn;
+      gc = gn;
+    }
+  }
+  // group: the best window over the lanes (larger mean, then smaller index),
+  // and the raw minimum and maximum
+  if constexpr (L >= 2) best_step<0xB1>(bacc, bcnt, bk);
+  if constexpr (L >= 4) best_step<0x4E>(bacc, bcnt, bk);
+  if constexpr (L >= 8) best_step<0x141>(bacc, bcnt, bk);
+  if constexpr (L >= 16) best_step<0x140>(bacc, bcnt, bk);
+  lo = int(gmin_u<L>(uint32_t(lo)));             // pixel values are >= 0
+  hi = 0xffff - int(gmin_u<L>(uint32_t(0xffff - hi)));
+  o4[0] = float(bk % w);
+  o4[1] = float(bk / w);
+  const double beta0 = double(lo), alpha0 = double(hi) - double(lo);
+  const double thr = __builtin_fma(alpha0, kExpMinusHalf, beta0);
+  int m = 0;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int c = li + L * j;
+    if (c >= w) continue;
+#pragma unroll 4
+    for (int r = 0; r < h; ++r) m += double(px[r * w + c]) > thr ? 1 : 0;
+  }
+  m = gsum_i<L>(m);
+  double sig = sqrt(double(m) / kPi);
+  sig = sig < 0.5 ? 0.5 : sig;
+  o4[2] = o4[3] = float(sig);
+}
+
+template <int L, int CPL, int DT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == SPOTFIT_U16 ? 3 : 1))) void
+peak_init_kernel(const void* data, int dtype,
                                                        const spotfit_shape_t* sizes,
                                                        const int64_t* offsets, int64_t n,
                                                        int max_side, int max_pixels, float* out) {
@@ -272,6 +359,13 @@ __global__ __launch_bounds__(64) void peak_init_kernel(const void* data, int dty
     }
     const int w = sh.w, h = sh.h;
     const int64_t off = offsets[s];
+    if constexpr (DT == SPOTFIT_U16) {
+      float o[4];
+      peak_init_u16<L, CPL>(static_cast<const uint16_t*>(data) + off, w, h, li, o);
+      if (li == 0)
+        for (int q = 0; q < 4; ++q) out[4 * s + q] = o[q];
+      continue;
+    }
     double best = -__builtin_inf();
     int bk = 0x7fffffff;
     float lo = __builtin_inff(), hi = -__builtin_inff();
@@ -364,16 +458,26 @@ hipError_t launch_start_values(int method, const void* data, int dtype, const sp
     else
       hipLaunchKernelGGL((ini::moment_init_kernel<16, 2>), grid, block, 0, st, data, dtype, sizes,
                          offsets, n, max_side, max_pixels, out);
+  } else if (dtype == SPOTFIT_U16) {
+    if (cls == 0)
+      hipLaunchKernelGGL((ini::peak_init_kernel<4, 2, SPOTFIT_U16>), grid, block, 0, st, data, dtype,
+                         sizes, offsets, n, max_side, max_pixels, out);
+    else if (cls == 1)
+      hipLaunchKernelGGL((ini::peak_init_kernel<4, 4, SPOTFIT_U16>), grid, block, 0, st, data, dtype,
+                         sizes, offsets, n, max_side, max_pixels, out);
+    else
+      hipLaunchKernelGGL((ini::peak_init_kernel<16, 2, SPOTFIT_U16>), grid, block, 0, st, data, dtype,
+                         sizes, offsets, n, max_side, max_pixels, out);
   } else {
     if (cls == 0)
-      hipLaunchKernelGGL((ini::peak_init_kernel<4, 2>), grid, block, 0, st, data, dtype, sizes,
-                         offsets, n, max_side, max_pixels, out);
+      hipLaunchKernelGGL((ini::peak_init_kernel<4, 2, SPOTFIT_F32>), grid, block, 0, st, data, dtype,
+                         sizes, offsets, n, max_side, max_pixels, out);
     else if (cls == 1)
-      hipLaunchKernelGGL((ini::peak_init_kernel<4, 4>), grid, block, 0, st, data, dtype, sizes,
-                         offsets, n, max_side, max_pixels, out);
+      hipLaunchKernelGGL((ini::peak_init_kernel<4, 4, SPOTFIT_F32>), grid, block, 0, st, data, dtype,
+                         sizes, offsets, n, max_side, max_pixels, out);
     else
-      hipLaunchKernelGGL((ini::peak_init_kernel<16, 2>), grid, block, 0, st, data, dtype, sizes,
-                         offsets, n, max_side, max_pixels, out);
+      hipLaunchKernelGGL((ini::peak_init_kernel<16, 2, SPOTFIT_F32>), grid, block, 0, st, data, dtype,
+                         sizes, offsets, n, max_side, max_pixels, out);
   }
   return hipGetLastError();
 }
