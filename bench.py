@@ -35,7 +35,7 @@ C_TRIAL = 16
 
 # the narrow fit kernel's source and the headers its code comes from
 FIT_KERNEL_SOURCES = ("spotfit_narrow.hip", "spotfit_internal.h", "spotfit_lm.h", "lanegroup.h",
-                      "xlane.h")
+                      "xlane.h", "spotfit_start.h")
 
 
 def kernel_source_hash() -> str:

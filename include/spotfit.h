@@ -214,6 +214,27 @@ int spotfit_peak_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                       const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n_spots,
                       const spotfit_options_t* opt, float* init_out, void* stream);
 
+/* Raw spots in, fits out, in one launch: the start values of
+ * spotfit_moment_init and the fit from them (the paper leaves start values to
+ * the caller, Results section; its fit is the Fit2DGaussian algorithm with
+ * Eqs. 5-14).  With opt->precision SPOTFIT_PREC_FP64 the fit kernel's own
+ * lane groups compute each spot's start values before they fit it, so no
+ * start-value pass and no round trip through memory sits between frame and
+ * fit; with the other precisions a start-value launch precedes the fit.
+ * init_out float[n][4] (device, caller-owned, required) receives the start
+ * values each fit began from (NaN for the shapes spotfit_moment_init rejects,
+ * whose fits end as BAD_INPUT).  They equal spotfit_moment_init's up to the
+ * order of its double-precision sums (bit for bit where the fit's lanes per
+ * spot match the start-value kernel's: the default plans of the uniform
+ * schedule), and the fit outputs are bit for bit those of spotfit_fit_spots
+ * with init = init_out and the same plan.  The other arguments, ownership,
+ * stream and return codes as spotfit_fit_spots. */
+int spotfit_fit_raw(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                    const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n_spots,
+                    const spotfit_options_t* opt, float* init_out, float* params_out,
+                    float* chi2_out, int32_t* iters_out, int32_t* status_out,
+                    int32_t* evals_out, void* stream);
+
 /* Stop reasons and iteration counts of a fitted batch: the statistics the
  * paper reports in its Number of iterations section (Fig. 8). */
 typedef struct {

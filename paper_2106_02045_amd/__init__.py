@@ -29,7 +29,8 @@ EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_
             "spotfit_serve_stats", "spotfit_serve_destroy", "spotfit_serve_replay",
             "spotfit_serve_last_error", "spotfit_get_stats", "spotfit_autotune",
             "spotfit_moment_init", "spotfit_peak_init", "spotfit_serve_track",
-            "spotfit_graph_create", "spotfit_graph_launch", "spotfit_graph_destroy"]
+            "spotfit_graph_create", "spotfit_graph_launch", "spotfit_graph_destroy",
+            "spotfit_fit_raw"]
 E_AGAIN = -6
 
 
@@ -166,6 +167,9 @@ def lib():
         L.spotfit_fit_spots.argtypes = [vp, vp, i32, vp, vp, vp, i64, ctypes.POINTER(Options),
                                         vp, vp, vp, vp, vp, vp]
         L.spotfit_fit_spots.restype = ctypes.c_int
+        L.spotfit_fit_raw.argtypes = [vp, vp, i32, vp, vp, i64, ctypes.POINTER(Options), vp,
+                                      vp, vp, vp, vp, vp, vp]
+        L.spotfit_fit_raw.restype = ctypes.c_int
         L.spotfit_last_error.argtypes = []
         L.spotfit_last_error.restype = ctypes.c_char_p
         L.spotfit_version.argtypes = []
@@ -329,6 +333,32 @@ class Context:
                                 st.cuda_stream)
         _check(rc, "spotfit_fit_spots")
         return out
+
+    def fit_raw(self, data, sizes, offsets, opts: Optional[Options] = None, out=None,
+                want_evals: bool = False, stream=None):
+        """Raw spots in, fits out (spotfit_fit_raw): the centroid / second-moment start
+        values and the fit from them, in the fit's own launch with the double-precision
+        kernels.  Returns fit_spots' outputs plus "init", float32 [n, 4]: the start
+        values each fit began from.  `out` may supply any of the outputs, "init" too."""
+        import torch
+        n = int(sizes.shape[0])
+        out = dict(out) if out is not None else {}
+        init = out.pop("init", None)
+        if init is None:
+            init = torch.empty((n, 4), dtype=torch.float32, device=data.device)
+        n, dt, res = self._marshal(data, sizes, offsets, init, out or None, want_evals)
+        st = stream if stream is not None else torch.cuda.current_stream(data.device)
+        rc = lib().spotfit_fit_raw(self._h, data.data_ptr(), dt, sizes.data_ptr(),
+                                   offsets.data_ptr(), n,
+                                   ctypes.byref(opts) if opts is not None else None,
+                                   init.data_ptr(), res["params"].data_ptr(),
+                                   res["chi2"].data_ptr(), res["iters"].data_ptr(),
+                                   res["status"].data_ptr(),
+                                   res["evals"].data_ptr() if "evals" in res else None,
+                                   st.cuda_stream or None)
+        _check(rc, "spotfit_fit_raw")
+        res["init"] = init
+        return res
 
     def graph(self, data, sizes, offsets, init, opts: Optional[Options] = None, out=None,
               host=None):

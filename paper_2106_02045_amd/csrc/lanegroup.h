@@ -1,5 +1,6 @@
 // lanegroup.h -- operations inside a group of L consecutive lanes (L = 1, 2, 4,
-// 8 or 16, aligned) of a gfx950 wavefront, by DPP or ds_swizzle.
+// 8 or 16, aligned; the totals and minima also L = 32) of a gfx950 wavefront,
+// by DPP, ds_swizzle or permlane16_swap.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -9,16 +10,26 @@
 namespace sf {
 namespace lg {
 
+// Both halves of a pair of 16-lane rows (lanes l and l ^ 16): permlane16_swap
+// of a value with itself gives the even row's value in [0] and the odd row's
+// in [1] on every lane of the pair.
+__device__ __forceinline__ void row_pair(uint32_t v, uint32_t& even, uint32_t& odd) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  even = r[0];
+  odd = r[1];
+}
+
 // Total over the group: butterfly over lane bits 0 (quad_perm [1,0,3,2]), 1
-// (quad_perm [2,3,0,1]), 2 (row_half_mirror) and 3 (row_mirror).  The two
-// partners of a step add the same two numbers, so every lane of the group
-// holds bitwise the same total.
+// (quad_perm [2,3,0,1]), 2 (row_half_mirror), 3 (row_mirror) and 4 (pairs of
+// rows).  The two partners of a step add the same two numbers, so every lane of
+// the group holds bitwise the same total.
 template <int L>
 __device__ __forceinline__ double gsum(double v) {
   if constexpr (L >= 2) v += dpp_mov<0xB1>(v);
   if constexpr (L >= 4) v += dpp_mov<0x4E>(v);
   if constexpr (L >= 8) v += dpp_mov<0x141>(v);
   if constexpr (L >= 16) v += dpp_mov<0x140>(v);
+  if constexpr (L >= 32) v = pair<1>(v, v);
   return v;
 }
 
@@ -33,6 +44,11 @@ __device__ __forceinline__ int gsum_i(int v) {
   if constexpr (L >= 4) v += dpp_i<0x4E>(v);
   if constexpr (L >= 8) v += dpp_i<0x141>(v);
   if constexpr (L >= 16) v += dpp_i<0x140>(v);
+  if constexpr (L >= 32) {
+    uint32_t e, o;
+    row_pair((uint32_t)v, e, o);
+    v = (int)e + (int)o;
+  }
   return v;
 }
 
@@ -43,6 +59,11 @@ __device__ __forceinline__ uint32_t gmin_u(uint32_t v) {
   if constexpr (L >= 4) { t = (uint32_t)dpp_i<0x4E>((int)v); v = t < v ? t : v; }
   if constexpr (L >= 8) { t = (uint32_t)dpp_i<0x141>((int)v); v = t < v ? t : v; }
   if constexpr (L >= 16) { t = (uint32_t)dpp_i<0x140>((int)v); v = t < v ? t : v; }
+  if constexpr (L >= 32) {
+    uint32_t e, o;
+    row_pair(v, e, o);
+    v = e < o ? e : o;
+  }
   return v;
 }
 

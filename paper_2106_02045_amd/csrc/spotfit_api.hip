@@ -308,17 +308,20 @@ int check_call(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   return SPOTFIT_OK;
 }
 
-// Enqueue one fit with validated options o and n > 0.
+// Enqueue one fit with validated options o and n > 0.  init_out not NULL (with
+// init NULL): the separable double-precision kernels compute the start values
+// themselves and write them there.
 int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
                const int64_t* offsets, const float* init, int64_t n, const spotfit_options_t& o,
                float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
-               int32_t* evals_out, void* stream) {
+               int32_t* evals_out, void* stream, float* init_out = nullptr) {
   sf::KArgs ka;
   std::memset(&ka, 0, sizeof ka);
   ka.data = data;
   ka.sizes = sizes;
   ka.offsets = offsets;
   ka.init = init;
+  ka.init_out = init_out;
   ka.params_out = params_out;
   ka.chi2_out = chi2_out;
   ka.iters_out = iters_out;
@@ -372,7 +375,8 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
       kc.n = n - c0 < chunk ? n - c0 : chunk;
       kc.sizes = sizes + c0;
       kc.offsets = offsets + c0;
-      kc.init = init + 4 * c0;
+      kc.init = init ? init + 4 * c0 : nullptr;
+      kc.init_out = init_out ? init_out + 4 * c0 : nullptr;
       kc.params_out = params_out + 6 * c0;
       kc.chi2_out = chi2_out + c0;
       kc.iters_out = iters_out + c0;
@@ -409,6 +413,27 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
   if (rc != SPOTFIT_OK || n == 0) return rc;
   return launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
                     status_out, evals_out, stream);
+}
+
+int spotfit_fit_raw(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                    const spotfit_shape_t* sizes, const int64_t* offsets, int64_t n,
+                    const spotfit_options_t* opt, float* init_out, float* params_out,
+                    float* chi2_out, int32_t* iters_out, int32_t* status_out,
+                    int32_t* evals_out, void* stream) {
+  spotfit_options_t o;
+  int rc = check_call(ctx, data, dtype, sizes, offsets, init_out, n, opt, params_out, chi2_out,
+                      iters_out, status_out, &o, "fit_raw");
+  if (rc != SPOTFIT_OK || n == 0) return rc;
+  if (o.precision == SPOTFIT_PREC_FP64)
+    return launch_fit(ctx, data, dtype, sizes, offsets, nullptr, n, o, params_out, chi2_out,
+                      iters_out, status_out, evals_out, stream, init_out);
+  // the other kernels take their start values from memory: a start-value launch first
+  const hipError_t e = sf::launch_start_values(sf::kInitMoments, data, dtype, sizes, offsets, n,
+                                               o.max_side, o.max_pixels, init_out,
+                                               (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "fit_raw: start-value kernel launch");
+  return launch_fit(ctx, data, dtype, sizes, offsets, init_out, n, o, params_out, chi2_out,
+                    iters_out, status_out, evals_out, stream);
 }
 
 static int start_values(int method, const char* what, const void* data, int32_t dtype,

@@ -37,6 +37,7 @@
 #include "spotfit.h"
 #include "spotfit_internal.h"
 #include "spotfit_lm.h"
+#include "spotfit_start.h"
 #include "xlane.h"
 
 namespace sf {
@@ -71,6 +72,15 @@ struct State {
   int64_t next;                     // next spot index, broadcast from the group's first lane
 };
 
+// Start values of one spot (ini::moment_init_spot), out of line: its registers
+// are then not allocated across the fit's loop, which only saves what it keeps
+// live around this call.
+template <int L, int CPL>
+__device__ __noinline__ void start_values_of(const void* data, int dtype, spotfit_shape_t sh,
+                                             int64_t off, int li, float* o4) {
+  ini::moment_init_spot<L, CPL>(data, dtype, sh, off, li, o4);
+}
+
 // Totals over the group of the first K values; written to red[0..K-1].
 template <int L, int K>
 __device__ __forceinline__ void group_sums_to(double (&v)[K], double* red, int li) {
@@ -104,8 +114,10 @@ __device__ __forceinline__ double group_sum1(double v) {
 //
 // Template parameters: L lanes per spot, CPL columns (and rows) per lane, so a
 // group holds spots with w, h <= L*CPL; WPE = minimum waves per SIMD the
-// register allocation must allow.
-template <int L, int CPL, class Src>
+// register allocation must allow.  RAW: each group computes its spot's start
+// values when it takes the spot (centroid and second moments, as the
+// start-value kernel does) and writes them to ka.init_out.
+template <int L, int CPL, bool RAW, class Src>
 __device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * CPL>* sts) {
   constexpr int G = 64 / L;       // groups (spots in flight) per wavefront
   constexpr int HM = L * CPL;     // largest side of a spot
@@ -130,48 +142,68 @@ __device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * 
 #pragma unroll
   for (int j = 0; j < CPL; ++j) ex[j] = eyo[j] = tcol[j] = t1c[j] = t2c[j] = 0.0;
 
+  // The current spot's pixels into g (0 outside the spot); returns the lane's
+  // sum of them.
+  auto load_spot = [&](int64_t off) {
+    double cs = 0.0;
+#pragma unroll
+    for (int r0 = 0; r0 < HM; r0 += kChunk) {
+#pragma unroll
+      for (int r = r0; r < r0 + kChunk; ++r) {
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int c = li + L * j;
+          float gv = 0.f;
+          if (r < h && c < w) {
+            gv = ka.dtype == SPOTFIT_U16
+                     ? float(static_cast<const uint16_t*>(ka.data)[off + r * w + c])
+                     : static_cast<const float*>(ka.data)[off + r * w + c];
+          }
+          g[j][r] = gv;
+          cs += double(gv);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return cs;
+  };
+
   // Fetch the next spot of this group, writing BAD_INPUT for unusable ones.
   auto fetch = [&]() {
     while (s >= 0) {
       const spotfit_shape_t sh = ka.sizes[s];
-      const float* in = ka.init + 4 * s;
-      const float i0 = in[0], i1 = in[1], i2 = in[2], i3 = in[3];
       const int mdl = sh.model;
       const bool ell = mdl == SPOTFIT_ELL;
-      const bool bad = sh.w < 3 || sh.h < 3 || sh.w > HM || sh.h > HM ||
-                       sh.w * sh.h > o.max_pixels || sh.w > o.max_side || sh.h > o.max_side ||
-                       (mdl != SPOTFIT_SYM && !ell) || !__builtin_isfinite(i0) ||
-                       !__builtin_isfinite(i1) || !__builtin_isfinite(i2) || !(i2 > 0.f) ||
-                       (ell && (!__builtin_isfinite(i3) || !(i3 > 0.f)));
+      const bool bad_shape = sh.w < 3 || sh.h < 3 || sh.w > HM || sh.h > HM ||
+                             sh.w * sh.h > o.max_pixels || sh.w > o.max_side ||
+                             sh.h > o.max_side || (mdl != SPOTFIT_SYM && !ell);
+      const int64_t off = ka.offsets[s];
+      const float nanf = __builtin_nanf("");
+      float iv[4] = {nanf, nanf, nanf, nanf};
+      if constexpr (RAW) {
+        if (!bad_shape) start_values_of<L, CPL>(ka.data, ka.dtype, sh, off, li, iv);
+        if (li == 0) {
+          float* io = ka.init_out + 4 * s;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) io[q] = iv[q];
+        }
+      } else {
+        const float* in = ka.init + 4 * s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) iv[q] = in[q];
+      }
+      const bool bad = bad_shape || !__builtin_isfinite(iv[0]) || !__builtin_isfinite(iv[1]) ||
+                       !__builtin_isfinite(iv[2]) || !(iv[2] > 0.f) ||
+                       (ell && (!__builtin_isfinite(iv[3]) || !(iv[3] > 0.f)));
       if (!bad) {
         w = sh.w;
         h = sh.h;
         sym = !ell;
-        S.pc[0] = i0;
-        S.pc[1] = i1;
-        S.pc[2] = i2;
-        S.pc[3] = ell ? (double)i3 : (double)i2;
-        const int64_t off = ka.offsets[s];
-        double cs = 0.0;
-#pragma unroll
-        for (int r0 = 0; r0 < HM; r0 += kChunk) {
-#pragma unroll
-          for (int r = r0; r < r0 + kChunk; ++r) {
-#pragma unroll
-            for (int j = 0; j < CPL; ++j) {
-              const int c = li + L * j;
-              float gv = 0.f;
-              if (r < h && c < w) {
-                gv = ka.dtype == SPOTFIT_U16
-                         ? float(static_cast<const uint16_t*>(ka.data)[off + r * w + c])
-                         : static_cast<const float*>(ka.data)[off + r * w + c];
-              }
-              g[j][r] = gv;
-              cs += double(gv);
-            }
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        S.pc[0] = iv[0];
+        S.pc[1] = iv[1];
+        S.pc[2] = iv[2];
+        S.pc[3] = ell ? (double)iv[3] : (double)iv[2];
+        const double cs = load_spot(off);
         S.Gs = group_sum1<L>(cs);
         S.Tme = o.max_error_per_px * double(w * h);
         k = o.lambda0_exp10;
@@ -527,12 +559,12 @@ struct StridedSrc {
   }
 };
 
-template <int L, int CPL, int WPE>
+template <int L, int CPL, int WPE, bool RAW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_group_kernel(KArgs ka) {
   constexpr int G = 64 / L;
   __shared__ State<L * CPL> sts[G];
   StridedSrc src{ka.n, (int64_t)blockIdx.x * G, (int64_t)gridDim.x * G};
-  fit_groups<L, CPL>(ka, src, sts);
+  fit_groups<L, CPL, RAW>(ka, src, sts);
 }
 
 
@@ -615,7 +647,7 @@ __global__ __launch_bounds__(256) void mixed_classify_kernel(const spotfit_shape
   }
 }
 
-template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE>
+template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE, bool RAW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_mixed_kernel(
     KArgs ka, MixedWs ws) {
   __shared__ union {
@@ -629,23 +661,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const int c = (start + q) % 3;
     QueueSrc src{ws.lists + (int64_t)c * ws.cap, ws.counters + 3 + c, ws.counters[c]};
     if (c == 0)
-      fit_groups<L0, C0>(ka, src, st.a);
+      fit_groups<L0, C0, RAW>(ka, src, st.a);
     else if (c == 1)
-      fit_groups<L1, C1>(ka, src, st.b);
+      fit_groups<L1, C1, RAW>(ka, src, st.b);
     else
-      fit_groups<L2, C2>(ka, src, st.c);
+      fit_groups<L2, C2, RAW>(ka, src, st.c);
   }
 }
 
 template <int L, int CPL, int WPE>
 static hipError_t launch_lw(const KArgs& ka, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((fit_group_kernel<L, CPL, WPE>), dim3(grid), dim3(64), 0, st, ka);
+  if (ka.init_out)
+    hipLaunchKernelGGL((fit_group_kernel<L, CPL, WPE, true>), dim3(grid), dim3(64), 0, st, ka);
+  else
+    hipLaunchKernelGGL((fit_group_kernel<L, CPL, WPE, false>), dim3(grid), dim3(64), 0, st, ka);
   return hipGetLastError();
 }
 
 template <int L, int CPL, int WPE>
 static const void* sym_lw() {
-  return reinterpret_cast<const void*>(&fit_group_kernel<L, CPL, WPE>);
+  return reinterpret_cast<const void*>(&fit_group_kernel<L, CPL, WPE, false>);
 }
 
 // The compiled plans: (lanes per spot, columns per lane, min waves per SIMD).
@@ -707,7 +742,7 @@ int mixed_plan_count() { return wide_mixed_plan_count() + narrow_mixed_plan_coun
 const void* mixed_kernel_symbol(int plan) {
   if (plan >= wide_mixed_plan_count()) return narrow_mixed_kernel_symbol(plan - wide_mixed_plan_count());
 #define SF_MSYM(I, A, B, C, D, E, F, W) \
-  if (plan == I) return reinterpret_cast<const void*>(&grp::fit_mixed_kernel<A, B, C, D, E, F, W>);
+  if (plan == I) return reinterpret_cast<const void*>(&grp::fit_mixed_kernel<A, B, C, D, E, F, W, false>);
   SF_MIXED_PLANS(SF_MSYM)
 #undef SF_MSYM
   return nullptr;
@@ -730,11 +765,15 @@ hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, 
   if (e != hipSuccess) return e;
   if (plan >= wide_mixed_plan_count())
     return launch_narrow_mixed_fit(plan - wide_mixed_plan_count(), ka, ws, grid, st);
-#define SF_MLAUNCH(I, A, B, C, D, E, F, W)                                                   \
-  if (plan == I) {                                                                           \
-    hipLaunchKernelGGL((grp::fit_mixed_kernel<A, B, C, D, E, F, W>), dim3(grid), dim3(64), 0, \
-                       st, ka, ws);                                                          \
-    return hipGetLastError();                                                                \
+#define SF_MLAUNCH(I, A, B, C, D, E, F, W)                                                          \
+  if (plan == I) {                                                                                  \
+    if (ka.init_out)                                                                                \
+      hipLaunchKernelGGL((grp::fit_mixed_kernel<A, B, C, D, E, F, W, true>), dim3(grid), dim3(64), \
+                         0, st, ka, ws);                                                            \
+    else                                                                                            \
+      hipLaunchKernelGGL((grp::fit_mixed_kernel<A, B, C, D, E, F, W, false>), dim3(grid), dim3(64), \
+                         0, st, ka, ws);                                                            \
+    return hipGetLastError();                                                                       \
   }
   SF_MIXED_PLANS(SF_MLAUNCH)
 #undef SF_MLAUNCH

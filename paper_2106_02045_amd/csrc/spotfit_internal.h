@@ -30,6 +30,7 @@ struct KArgs {
   const spotfit_shape_t* sizes;
   const int64_t* offsets;
   const float* init;
+  float* init_out;  // not NULL: start values computed in the fit launch, written here
   float* params_out;
   float* chi2_out;
   int32_t* iters_out;

@@ -38,6 +38,7 @@
 #include "spotfit_internal.h"
 #include "lanegroup.h"
 #include "spotfit_lm.h"
+#include "spotfit_start.h"
 
 namespace sf {
 namespace nrw {
@@ -103,11 +104,31 @@ __device__ __forceinline__ double pixel(uint32_t v) {
     return double(__uint_as_float(v));
 }
 
+// Start values of one spot (ini::moment_init_spot), out of line: its registers
+// are then not allocated across the fit's loop, which only saves what it keeps
+// live around this call.
+template <int L, int CPL, int DT>
+__device__ __noinline__ void start_values_of(const void* data, spotfit_shape_t sh, int64_t off,
+                                             int li, float* o4) {
+  ini::moment_init_spot<L, CPL>(data, DT, sh, off, li, o4);
+}
+
+// Orders this wavefront's LDS writes before its later LDS reads (a workgroup
+// is one wavefront).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Fit every spot the source hands to this wavefront's groups.
 // L lanes per spot, CPL columns per lane: spots with w, h <= L * CPL; pixel
-// data type DT (SPOTFIT_U16 or SPOTFIT_F32).
-template <int L, int CPL, int DT>
-__device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, NState* sts) {
+// data type DT (SPOTFIT_U16 or SPOTFIT_F32).  RAW: the start values are
+// computed here (centroid and second moments, as the start-value kernel does)
+// and written to ka.init_out; cinit is LDS for two chunks of them.
+template <int L, int CPL, int DT, bool RAW>
+__device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, NState* sts,
+                                           float4* cinit) {
   constexpr int HM = L * CPL;
   const int lane = __lane_id();
   const int gi = lane / L;
@@ -151,30 +172,75 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
   constexpr int kChunk = 64 / L;
   int cbase = 0, cused = 0, nbase_l0 = 0;
   bool nb_asked = false;
+  // RAW: the wavefront computes the start values of a whole chunk at once, every
+  // group one spot with all lanes active, into cinit[kChunk * buffer + position
+  // in the chunk]; buffer cb holds the current chunk's, the other the next
+  // chunk's once its base is known (nb_ready).
+  int cb = 0;
+  bool nb_ready = false;
+  auto chunk_start = [&](int base, int buf) {
+    const int p = base + gi;
+    const int64_t id =
+        (uint32_t)p < (uint32_t)q.count ? (q.list ? (int64_t)q.list[p] : (int64_t)p) : -1;
+    const float nanf = __builtin_nanf("");
+    float o4[4] = {nanf, nanf, nanf, nanf};
+    if (id >= 0) {
+      const spotfit_shape_t sh = ka.sizes[id];
+      if (ini::usable<HM>(sh, o.max_side, o.max_pixels))
+        start_values_of<L, CPL, DT>(ka.data, sh, ka.offsets[id], li, o4);
+      if (li == 0) {
+        float* io = ka.init_out + 4 * id;
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) io[q2] = o4[q2];
+      }
+    }
+    if (li == 0) cinit[kChunk * buf + gi] = make_float4(o4[0], o4[1], o4[2], o4[3]);
+    wave_lds_sync();
+  };
   {
     int b0 = 0;
     if (lane == 0) b0 = atomicAdd(q.take, kChunk);
     cbase = __builtin_amdgcn_readfirstlane(b0);
   }
+  if constexpr (RAW) chunk_start(cbase, 0);
   // Give every group with `want` a new reserved spot.  Called with the whole
   // wavefront active (the chunk state is wavefront-uniform).
   auto reserve = [&](bool want) {
     const bool req = want && li == 0;
     const uint64_t m = __builtin_amdgcn_ballot_w64(req);
     const int nreq = __builtin_popcountll(m);
+    if constexpr (RAW) {
+      // the next chunk's start values as soon as its base is back (or now, when
+      // this call already takes from it)
+      if (!nb_asked && cused + nreq > kChunk) {
+        if (lane == 0) nbase_l0 = atomicAdd(q.take, kChunk);
+        nb_asked = true;
+      }
+      if (nb_asked && !nb_ready) {
+        chunk_start(__builtin_amdgcn_readfirstlane(nbase_l0), cb ^ 1);
+        nb_ready = true;
+      }
+    }
     if (nreq == 0) return;
     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    int pos;
+    int pos, slot = 0;
     if (cused + nreq > kChunk) {  // nreq <= kChunk: the rest comes from the next chunk
       if (!nb_asked && lane == 0) nbase_l0 = atomicAdd(q.take, kChunk);
       const int nb = __builtin_amdgcn_readfirstlane(nbase_l0);
-      pos = cused + rank < kChunk ? cbase + cused + rank : nb + (cused + rank - kChunk);
+      const bool here = cused + rank < kChunk;
+      pos = here ? cbase + cused + rank : nb + (cused + rank - kChunk);
+      if constexpr (RAW) {
+        slot = here ? kChunk * cb + cused + rank : kChunk * (cb ^ 1) + (cused + rank - kChunk);
+        cb ^= 1;
+        nb_ready = false;
+      }
       cbase = nb;
       cused = cused + nreq - kChunk;
       nb_asked = false;
     } else {
       pos = cbase + cused + rank;
+      if constexpr (RAW) slot = kChunk * cb + cused + rank;
       cused += nreq;
     }
     if (!nb_asked && 2 * cused >= kChunk) {
@@ -182,13 +248,18 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
       nb_asked = true;
     }
     const int p = gbcast_i<L, 0>(req ? pos : 0);
+    const int sl = RAW ? gbcast_i<L, 0>(req ? slot : 0) : 0;
     if (want) {
       ns = (uint32_t)p < (uint32_t)q.count ? (q.list ? (int64_t)q.list[p] : (int64_t)p) : -1;
       if (ns >= 0) {
         nsh = ka.sizes[ns];
         noff = ka.offsets[ns];
-        const float* in = ka.init + 4 * ns;
-        nin = make_float4(in[0], in[1], in[2], in[3]);
+        if constexpr (RAW) {
+          nin = cinit[sl];
+        } else {
+          const float* in = ka.init + 4 * ns;
+          nin = make_float4(in[0], in[1], in[2], in[3]);
+        }
       }
     }
   };
@@ -662,19 +733,21 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
   }
 }
 
-template <int L, int CPL, int WPE, int DT>
+template <int L, int CPL, int WPE, int DT, bool RAW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_narrow_kernel(KArgs ka) {
   __shared__ NState sts[64 / L];
-  fit_narrow<L, CPL, DT>(ka, SpotQueue{nullptr, ka.queue, (int32_t)ka.n}, sts);
+  __shared__ float4 cinit[RAW ? 2 * (64 / L) : 1];
+  fit_narrow<L, CPL, DT, RAW>(ka, SpotQueue{nullptr, ka.queue, (int32_t)ka.n}, sts, cinit);
 }
 
 // Batches of uneven spot sizes: the classify pass of the wide kernel's mixed
 // launch buckets spots by size class; each wavefront runs the plan of one class
 // and moves on to the next class when that class's list runs dry.
-template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE, int DT>
+template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE, int DT, bool RAW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_narrow_mixed_kernel(
     KArgs ka, MixedWs ws) {
   __shared__ NState sts[64 / L0];
+  __shared__ float4 cinit[RAW ? 2 * (64 / L0) : 1];
   static_assert(L0 <= L1 && L1 <= L2, "classes in order of size");
   const int start = blockIdx.x % 3;
   for (int q = 0; q < 3; ++q) {
@@ -683,11 +756,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     int32_t* take = ws.counters + 3 + c;
     const int32_t count = ws.counters[c];
     if (c == 0)
-      fit_narrow<L0, C0, DT>(ka, SpotQueue{list, take, count}, sts);
+      fit_narrow<L0, C0, DT, RAW>(ka, SpotQueue{list, take, count}, sts, cinit);
     else if (c == 1)
-      fit_narrow<L1, C1, DT>(ka, SpotQueue{list, take, count}, sts);
+      fit_narrow<L1, C1, DT, RAW>(ka, SpotQueue{list, take, count}, sts, cinit);
     else
-      fit_narrow<L2, C2, DT>(ka, SpotQueue{list, take, count}, sts);
+      fit_narrow<L2, C2, DT, RAW>(ka, SpotQueue{list, take, count}, sts, cinit);
   }
 }
 
@@ -717,7 +790,7 @@ void narrow_plan_shape(int plan, int* lanes, int* cpl) {
 
 const void* narrow_kernel_symbol(int plan) {
 #define SF_NSYM(I, L, C, W) \
-  if (plan == I) return reinterpret_cast<const void*>(&nrw::fit_narrow_kernel<L, C, W, SPOTFIT_U16>);
+  if (plan == I) return reinterpret_cast<const void*>(&nrw::fit_narrow_kernel<L, C, W, SPOTFIT_U16, false>);
   SF_NARROW_PLANS(SF_NSYM)
 #undef SF_NSYM
   return nullptr;
@@ -732,7 +805,7 @@ int narrow_mixed_plan_count() { return 1; }
 const void* narrow_mixed_kernel_symbol(int plan) {
 #define SF_NMSYM(I, A, B, C, D, E, F, W) \
   if (plan == I)                         \
-    return reinterpret_cast<const void*>(&nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_U16>);
+    return reinterpret_cast<const void*>(&nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_U16, false>);
   SF_NARROW_MIXED_PLANS(SF_NMSYM)
 #undef SF_NMSYM
   return nullptr;
@@ -740,15 +813,22 @@ const void* narrow_mixed_kernel_symbol(int plan) {
 
 hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid,
                                    hipStream_t st) {
-#define SF_NMLAUNCH(I, A, B, C, D, E, F, W)                                                      \
-  if (plan == I) {                                                                               \
-    if (ka.dtype == SPOTFIT_U16)                                                                 \
-      hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_U16>),       \
-                         dim3(grid), dim3(64), 0, st, ka, ws);                                   \
-    else                                                                                         \
-      hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_F32>),       \
-                         dim3(grid), dim3(64), 0, st, ka, ws);                                   \
-    return hipGetLastError();                                                                  \
+  const bool raw = ka.init_out != nullptr;
+#define SF_NMLAUNCH(I, A, B, C, D, E, F, W)                                                     \
+  if (plan == I) {                                                                              \
+    if (ka.dtype == SPOTFIT_U16 && raw)                                                         \
+      hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_U16, true>), \
+                         dim3(grid), dim3(64), 0, st, ka, ws);                                  \
+    else if (ka.dtype == SPOTFIT_U16)                                                           \
+      hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_U16, false>), \
+                         dim3(grid), dim3(64), 0, st, ka, ws);                                  \
+    else if (raw)                                                                               \
+      hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_F32, true>), \
+                         dim3(grid), dim3(64), 0, st, ka, ws);                                  \
+    else                                                                                        \
+      hipLaunchKernelGGL((nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_F32, false>), \
+                         dim3(grid), dim3(64), 0, st, ka, ws);                                  \
+    return hipGetLastError();                                                                 \
   }
   SF_NARROW_MIXED_PLANS(SF_NMLAUNCH)
 #undef SF_NMLAUNCH
@@ -763,15 +843,22 @@ hipError_t launch_narrow_kernel(int plan, const KArgs& ka, int grid, hipStream_t
   hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, ka.queue);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-#define SF_NLAUNCH(I, L, C, W)                                                                \
-  if (plan == I) {                                                                            \
-    if (ka.dtype == SPOTFIT_U16)                                                              \
-      hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W, SPOTFIT_U16>), dim3(grid), dim3(64), \
-                         0, st, ka);                                                          \
-    else                                                                                      \
-      hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W, SPOTFIT_F32>), dim3(grid), dim3(64), \
-                         0, st, ka);                                                          \
-    return hipGetLastError();                                                                \
+  const bool raw = ka.init_out != nullptr;
+#define SF_NLAUNCH(I, L, C, W)                                                                      \
+  if (plan == I) {                                                                                  \
+    if (ka.dtype == SPOTFIT_U16 && raw)                                                             \
+      hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W, SPOTFIT_U16, true>), dim3(grid), dim3(64), \
+                         0, st, ka);                                                                \
+    else if (ka.dtype == SPOTFIT_U16)                                                               \
+      hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W, SPOTFIT_U16, false>), dim3(grid),          \
+                         dim3(64), 0, st, ka);                                                      \
+    else if (raw)                                                                                   \
+      hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W, SPOTFIT_F32, true>), dim3(grid), dim3(64), \
+                         0, st, ka);                                                                \
+    else                                                                                            \
+      hipLaunchKernelGGL((nrw::fit_narrow_kernel<L, C, W, SPOTFIT_F32, false>), dim3(grid),          \
+                         dim3(64), 0, st, ka);                                                      \
+    return hipGetLastError();                                                                      \
   }
   SF_NARROW_PLANS(SF_NLAUNCH)
 #undef SF_NLAUNCH

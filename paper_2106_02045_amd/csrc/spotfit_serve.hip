@@ -242,16 +242,19 @@ bool spotfit_serve::launch_ready() {
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_offs + spot0, h_offs + spot0, sizeof(int64_t) * nsp, hipMemcpyHostToDevice, st);
   int rc = SPOTFIT_OK;
-  if (e == hipSuccess && dev_init)
-    rc = spotfit_moment_init(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0, nsp, &opt,
-                             d_init + 4 * spot0, st);
-  else if (e == hipSuccess)
+  if (e == hipSuccess && dev_init) {
+    // start values on the device, in the fit's own launch
+    rc = spotfit_fit_raw(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0, nsp, &opt,
+                         d_init + 4 * spot0, d_params + 6 * spot0, d_chi2 + spot0, d_iters + spot0,
+                         d_status + spot0, nullptr, st);
+  } else if (e == hipSuccess) {
     e = hipMemcpyAsync(d_init + 4 * spot0, h_init + 4 * spot0, sizeof(float) * 4 * nsp,
                        hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && rc == SPOTFIT_OK)
-    rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0, d_init + 4 * spot0,
-                           nsp, &opt, d_params + 6 * spot0, d_chi2 + spot0, d_iters + spot0,
-                           d_status + spot0, nullptr, st);
+    if (e == hipSuccess)
+      rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0,
+                             d_init + 4 * spot0, nsp, &opt, d_params + 6 * spot0, d_chi2 + spot0,
+                             d_iters + spot0, d_status + spot0, nullptr, st);
+  }
   int n_tracked = 0;
   if (e == hipSuccess && rc == SPOTFIT_OK && track_markers > 0) {
     sf::TrackFrame* tf = h_tf[si];

@@ -8,6 +8,11 @@ Per workload and method (moment: centroid / second moments; peak: the paper's
 time over 20 calls (HIP events on the stream), spots/s, and the algorithmic
 bytes per call (pixels + 4 B shape + 8 B offset read, 16 B start values
 written per spot) over that time against 8 TB/s.  One JSON line each.
+
+With --raw: raw spots to fits, per workload: the fit alone from given start
+values, the start-value kernel followed by the fit (two launches), and
+spotfit_fit_raw (start values computed inside the fit's launch); average time
+per call over --reps calls (HIP events on the stream).
 """
 from __future__ import annotations
 
@@ -29,6 +34,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workloads", default="scale_15x15,precision_32x32_ell")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--raw", action="store_true", help="time raw spots to fits instead")
+    ap.add_argument("--plan", choices=["throughput", "latency"], default="throughput")
+    ap.add_argument("--spots", default="", help="with --raw: comma list of batch sizes "
+                    "(the first spots of each workload; default: the whole workload)")
     a = ap.parse_args(argv)
 
     import torch
@@ -39,6 +48,46 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     ctx = sf.Context(0)
     st = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(a.reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / a.reps
+
+    if a.raw:
+        sizes = [int(x) for x in a.spots.split(",") if x] or [None]
+        for name, n_spots in ((w, k) for w in a.workloads.split(",") for k in sizes):
+            b = spotgen.workload(name, n=n_spots, threads=16)
+            up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+            d = (up(b.data), up(b.sizes), up(b.offsets))
+            side = int(max(b.sizes[:, 0].max(), b.sizes[:, 1].max()))
+            uneven = len(np.unique(np.maximum(b.sizes[:, 0], b.sizes[:, 1]))) > 1
+            opts = sf.default_options(
+                max_side=max(3, side),
+                schedule=sf.SCHEDULE_MIXED if uneven else sf.SCHEDULE_UNIFORM,
+                plan_hint=sf.PLAN_LATENCY if a.plan == "latency" else sf.PLAN_THROUGHPUT)
+            init = ctx.moment_init(*d, opts)
+            out = ctx.fit_spots(*d, init, opts)
+            out_raw = dict(out, init=torch.empty_like(init))
+            t_fit = timed(lambda: ctx.fit_spots(*d, init, opts, out=out))
+            t_two = timed(lambda: (ctx.moment_init(*d, opts, out=init),
+                                   ctx.fit_spots(*d, init, opts, out=out)))
+            t_raw = timed(lambda: ctx.fit_raw(*d, opts, out=out_raw))
+            same = bool(torch.equal(out_raw["status"], out["status"]))
+            print(json.dumps({"workload": name, "spots": b.n, "plan": a.plan,
+                              "schedule": "mixed" if uneven else "uniform",
+                              "fit_ms": t_fit, "init_then_fit_ms": t_two, "fit_raw_ms": t_raw,
+                              "fits_per_s_raw": b.n / t_raw * 1e3,
+                              "status_same_as_two_calls": same}), flush=True)
+        return
+
     for name in a.workloads.split(","):
         b = spotgen.workload(name, threads=16)
         up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)

@@ -87,9 +87,8 @@ def main(argv=None):
     for f in check:
         b = frames[f]
         up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-        init = (ctx.moment_init(up(b.data), up(b.sizes), up(b.offsets), opts) if a.device_init
-                else up(b.init))
-        g = ctx.fit_spots(up(b.data), up(b.sizes), up(b.offsets), init, opts)
+        d = (up(b.data), up(b.sizes), up(b.offsets))
+        g = ctx.fit_raw(*d, opts) if a.device_init else ctx.fit_spots(*d, up(b.init), opts)
         torch.cuda.synchronize()
         same = (np.array_equal(g["params"].cpu().numpy(), outs[f]["params"]) and
                 np.array_equal(g["status"].cpu().numpy(), outs[f]["status"]) and

@@ -96,6 +96,15 @@ def test_call_level_errors_before_any_gpu_call():
     # NULL arrays with n > 0
     assert L.spotfit_fit_spots(fake, None, 0, 1, 1, 1, 10, None, 1, 1, 1, 1, None, None) == -1
     assert L.spotfit_fit_spots(fake, 1, 0, 1, 1, 1, 10, None, 1, None, 1, 1, None, None) == -1
+    # the raw-spots entry point checks the same way; init_out is required
+    args = lambda ctx, n, dt, opt, init_out: (ctx, 1, dt, 1, 1, n, opt, init_out, 1, 1, 1, 1,
+                                               None, None)
+    assert L.spotfit_fit_raw(*args(None, 10, 0, ctypes.byref(o), 1)) == -1
+    assert L.spotfit_fit_raw(*args(fake, -5, 0, ctypes.byref(o), 1)) == -2
+    assert L.spotfit_fit_raw(*args(fake, 10, 9, ctypes.byref(o), 1)) == -2
+    assert L.spotfit_fit_raw(*args(fake, 10, 0, ctypes.byref(bad), 1)) == -3
+    assert L.spotfit_fit_raw(*args(fake, 10, 0, ctypes.byref(o), None)) == -1
+    assert L.spotfit_fit_raw(*args(fake, 0, 0, ctypes.byref(o), None)) == 0
     assert L.spotfit_ctx_create(None, 0) == -1
     assert L.spotfit_ctx_reserve(None, 10) == -1
     assert L.spotfit_ctx_reserve(fake, -1) == -2

@@ -107,8 +107,9 @@ def test_serving_admission_by_memory(sf):
 
 
 def test_serving_with_device_start_values(sf):
-    # frames without start values: the loop computes them on the device; the
-    # results equal a direct moment_init + fit of the same spots, bit for bit
+    # frames without start values: the loop computes them on the device, inside
+    # the fit's launch; the results equal a direct fit_raw of the same spots, bit
+    # for bit, and the fit from those start values
     import torch
     ts, frames = spotgen.serve_frames(120, fps=5000.0, seed=11, threads=8)
     opts = sf.default_options(max_side=21, schedule=sf.SCHEDULE_MIXED)
@@ -124,11 +125,12 @@ def test_serving_with_device_start_values(sf):
     for f in range(0, len(frames), 17):
         b = frames[f]
         d = (up(b.data), up(b.sizes), up(b.offsets))
-        init = ctx.moment_init(*d, opts)
-        g = ctx.fit_spots(*d, init, opts)
+        g = ctx.fit_raw(*d, opts)
+        g2 = ctx.fit_spots(*d, g["init"], opts)
         torch.cuda.synchronize()
         for k in ("params", "chi2", "iters", "status"):
             np.testing.assert_array_equal(g[k].cpu().numpy(), outs[f][k])
+            np.testing.assert_array_equal(g2[k].cpu().numpy(), outs[f][k])
 
 
 def test_latency_plan_in_serving_matches_direct_calls(sf):
