@@ -307,8 +307,12 @@ typedef struct {
  * spotfit_graph_launch.  The capture runs on a private stream and launches
  * nothing; the mixed schedule's workspace is reserved beforehand.  Replays use
  * the context's buffers: do not overlap them with other calls on the same
- * context.  n_spots must be > 0.  Returns SPOTFIT_OK or a negative
- * spotfit_error_t. */
+ * context.  init may be NULL: the graph then computes the start values on
+ * the device as spotfit_fit_raw does (inside the fit's launch for the
+ * double-precision kernels), into a buffer of n x 4 floats it allocates here
+ * and frees in spotfit_graph_destroy, so that a replay takes raw pixels to
+ * fits (io->init must then be NULL).  n_spots must be > 0.  Returns SPOTFIT_OK
+ * or a negative spotfit_error_t. */
 int spotfit_graph_create(spotfit_graph_t** g, spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                          const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
                          int64_t n_spots, const spotfit_options_t* opt, float* params_out,

@@ -284,11 +284,14 @@ class Context:
             raise TypeError(f"data must be uint16 or float32, got {data.dtype}")
         for name, t, want in (("sizes", sizes, torch.uint8), ("offsets", offsets, torch.int64),
                               ("init", init, torch.float32)):
+            if t is None and name == "init":
+                continue
             if t.dtype != want or not t.is_contiguous() or t.device != dev:
                 raise TypeError(f"{name} must be a contiguous {want} tensor on {dev}")
         if not data.is_contiguous():
             raise TypeError("data must be contiguous")
-        if sizes.dim() != 2 or sizes.shape[1] != 4 or init.shape != (n, 4) or offsets.shape != (n,):
+        if (sizes.dim() != 2 or sizes.shape[1] != 4 or offsets.shape != (n,)
+                or (init is not None and init.shape != (n, 4))):
             raise ValueError("shape mismatch: sizes [n,4], offsets [n], init [n,4]")
         if out is None:
             out = dict(params=torch.empty((n, 6), dtype=torch.float32, device=dev),
@@ -367,8 +370,12 @@ class Context:
         The device tensors (and `out`, allocated if None) are baked into the graph: refill
         them between launches.  host: optional dict of PINNED CPU tensors with keys
         data, init (copied to the device before the fit) and params, chi2, iters, status
-        (copied back after it).  Returns a Graph whose launch() replays the whole call."""
+        (copied back after it).  init None: the graph computes the start values on the
+        device (as fit_raw does) and a replay takes raw pixels to fits.  Returns a Graph
+        whose launch() replays the whole call."""
         n, dt, out = self._marshal(data, sizes, offsets, init, out, False)
+        if init is None and host and "init" in host:
+            raise ValueError("host['init'] needs a device init tensor")
         io = None
         host = dict(host or {})
         if host:
@@ -379,7 +386,8 @@ class Context:
                     raise TypeError(f"host[{k!r}] must be a contiguous pinned CPU tensor")
             for k in ("init", "params", "chi2", "iters", "status"):
                 ref = init if k == "init" else out[k]
-                if k in host and (host[k].shape != ref.shape or host[k].dtype != ref.dtype):
+                if k in host and ref is not None and (host[k].shape != ref.shape
+                                                      or host[k].dtype != ref.dtype):
                     raise ValueError(f"host[{k!r}] must match {tuple(ref.shape)} {ref.dtype}")
             if "data" in host and (host["data"].dtype != data.dtype
                                    or host["data"].numel() != data.numel()):
@@ -390,7 +398,8 @@ class Context:
                          ptr("iters"), ptr("status"))
         h = ctypes.c_void_p()
         rc = lib().spotfit_graph_create(ctypes.byref(h), self._h, data.data_ptr(), dt,
-                                        sizes.data_ptr(), offsets.data_ptr(), init.data_ptr(), n,
+                                        sizes.data_ptr(), offsets.data_ptr(),
+                                        init.data_ptr() if init is not None else None, n,
                                         ctypes.byref(opts) if opts is not None else None,
                                         out["params"].data_ptr(), out["chi2"].data_ptr(),
                                         out["iters"].data_ptr(), out["status"].data_ptr(),

@@ -290,7 +290,7 @@ namespace {
 int check_call(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
                const int64_t* offsets, const float* init, int64_t n, const spotfit_options_t* opt,
                float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
-               spotfit_options_t* o, const char* who) {
+               spotfit_options_t* o, const char* who, bool init_optional = false) {
   if (!ctx) return fail(SPOTFIT_E_NULL, (std::string(who) + ": NULL context").c_str());
   if (n < 0) return fail(SPOTFIT_E_ARG, (std::string(who) + ": n_spots < 0").c_str());
   if (dtype != SPOTFIT_U16 && dtype != SPOTFIT_F32)
@@ -303,7 +303,8 @@ int check_call(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   int rc = spotfit_validate_options(o);
   if (rc != SPOTFIT_OK) return rc;
   if (n == 0) return SPOTFIT_OK;
-  if (!data || !sizes || !offsets || !init || !params_out || !chi2_out || !iters_out || !status_out)
+  if (!data || !sizes || !offsets || (!init && !init_optional) || !params_out || !chi2_out ||
+      !iters_out || !status_out)
     return fail(SPOTFIT_E_NULL, (std::string(who) + ": NULL array").c_str());
   return SPOTFIT_OK;
 }
@@ -398,6 +399,24 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   return SPOTFIT_OK;
 }
 
+// Enqueue start values and fit (validated options o, n > 0): in the fit's own
+// launch for the separable double-precision kernels, else a start-value
+// launch first (the other kernels read their start values from memory).
+int launch_raw(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
+               const int64_t* offsets, int64_t n, const spotfit_options_t& o, float* init_out,
+               float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
+               int32_t* evals_out, void* stream) {
+  if (o.precision == SPOTFIT_PREC_FP64)
+    return launch_fit(ctx, data, dtype, sizes, offsets, nullptr, n, o, params_out, chi2_out,
+                      iters_out, status_out, evals_out, stream, init_out);
+  const hipError_t e = sf::launch_start_values(sf::kInitMoments, data, dtype, sizes, offsets, n,
+                                               o.max_side, o.max_pixels, init_out,
+                                               (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "start-value kernel launch");
+  return launch_fit(ctx, data, dtype, sizes, offsets, init_out, n, o, params_out, chi2_out,
+                    iters_out, status_out, evals_out, stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -424,15 +443,7 @@ int spotfit_fit_raw(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
   int rc = check_call(ctx, data, dtype, sizes, offsets, init_out, n, opt, params_out, chi2_out,
                       iters_out, status_out, &o, "fit_raw");
   if (rc != SPOTFIT_OK || n == 0) return rc;
-  if (o.precision == SPOTFIT_PREC_FP64)
-    return launch_fit(ctx, data, dtype, sizes, offsets, nullptr, n, o, params_out, chi2_out,
-                      iters_out, status_out, evals_out, stream, init_out);
-  // the other kernels take their start values from memory: a start-value launch first
-  const hipError_t e = sf::launch_start_values(sf::kInitMoments, data, dtype, sizes, offsets, n,
-                                               o.max_side, o.max_pixels, init_out,
-                                               (hipStream_t)stream);
-  if (e != hipSuccess) return fail_hip(e, "fit_raw: start-value kernel launch");
-  return launch_fit(ctx, data, dtype, sizes, offsets, init_out, n, o, params_out, chi2_out,
+  return launch_raw(ctx, data, dtype, sizes, offsets, n, o, init_out, params_out, chi2_out,
                     iters_out, status_out, evals_out, stream);
 }
 
@@ -599,6 +610,7 @@ struct spotfit_graph {
   int device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  float* init_buf = nullptr;  // start values of a graph that computes them (init NULL)
 };
 
 extern "C" {
@@ -612,9 +624,12 @@ int spotfit_graph_create(spotfit_graph_t** out, spotfit_ctx_t* ctx, const void* 
   *out = nullptr;
   spotfit_options_t o;
   int rc = check_call(ctx, data, dtype, sizes, offsets, init, n, opt, params_out, chi2_out,
-                      iters_out, status_out, &o, "graph_create");
+                      iters_out, status_out, &o, "graph_create", true);
   if (rc != SPOTFIT_OK) return rc;
   if (n == 0) return fail(SPOTFIT_E_ARG, "graph_create: n_spots = 0");
+  const bool raw = init == nullptr;  // start values computed on the device
+  if (raw && io && io->init)
+    return fail(SPOTFIT_E_ARG, "graph_create: io->init needs a device init array");
   if (io && io->data && io->data_bytes <= 0)
     return fail(SPOTFIT_E_ARG, "graph_create: io->data_bytes must be > 0 with io->data");
   // the caller's current device is restored on return
@@ -635,10 +650,18 @@ int spotfit_graph_create(spotfit_graph_t** out, spotfit_ctx_t* ctx, const void* 
   spotfit_graph* g = new (std::nothrow) spotfit_graph();
   if (!g) return fail(SPOTFIT_E_ARG, "graph_create: out of host memory");
   g->device = ctx->device;
+  if (raw) {
+    e = hipMalloc((void**)&g->init_buf, sizeof(float) * 4 * (size_t)n);
+    if (e != hipSuccess) {
+      g->init_buf = nullptr;
+      spotfit_graph_destroy(g);
+      return fail_hip(e, "hipMalloc (graph start values)");
+    }
+  }
   hipStream_t st = nullptr;
   e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   if (e != hipSuccess) {
-    delete g;
+    spotfit_graph_destroy(g);
     return fail_hip(e, "hipStreamCreateWithFlags");
   }
   e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
@@ -649,7 +672,10 @@ int spotfit_graph_create(spotfit_graph_t** out, spotfit_ctx_t* ctx, const void* 
     e = hipMemcpyAsync(const_cast<float*>(init), io->init, sizeof(float) * 4 * (size_t)n,
                        hipMemcpyHostToDevice, st);
   rc = SPOTFIT_OK;
-  if (e == hipSuccess)
+  if (e == hipSuccess && raw)
+    rc = launch_raw(ctx, data, dtype, sizes, offsets, n, o, g->init_buf, params_out, chi2_out,
+                    iters_out, status_out, nullptr, st);
+  else if (e == hipSuccess)
     rc = launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
                     status_out, nullptr, st);
   if (e == hipSuccess && rc == SPOTFIT_OK && io && io->params)
@@ -686,6 +712,7 @@ void spotfit_graph_destroy(spotfit_graph_t* g) {
   (void)hipSetDevice(g->device);
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->init_buf) (void)hipFree(g->init_buf);
   delete g;
 }
 

@@ -8,6 +8,8 @@ copy the frame's pixels and start values from pinned host memory, fit, copy the
 results back, synchronise.  Graph: the same sequence captured once
 (spotfit_graph_create with host copies) and replayed with one launch per frame.
 Prints one JSON line per (plan, mode) with p50 / p99 of the per-frame time.
+With --raw the frames carry no start values: direct calls spotfit_fit_raw and
+the graph is captured with init NULL (start values computed on the device).
 """
 from __future__ import annotations
 
@@ -28,6 +30,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--frames", type=int, default=5000)
     ap.add_argument("--markers", type=int, default=32)
+    ap.add_argument("--raw", action="store_true", help="frames without start values")
     a = ap.parse_args(argv)
 
     import torch
@@ -48,18 +51,24 @@ def main(argv=None):
                 chi2=torch.empty(n, dtype=torch.float32).pin_memory(),
                 iters=torch.empty(n, dtype=torch.int32).pin_memory(),
                 status=torch.empty(n, dtype=torch.int32).pin_memory())
+    if a.raw:
+        del host["init"]
     st = torch.cuda.current_stream(dev)
     for plan in ("latency", "throughput"):
         opts = sf.default_options(max_side=13, plan_hint=sf.PLAN_LATENCY if plan == "latency"
                                   else sf.PLAN_THROUGHPUT)
         out = {k: torch.empty_like(v, device=dev) for k, v in host.items()
                if k in ("params", "chi2", "iters", "status")}
-        g = ctx.graph(d["data"], d["sizes"], d["offsets"], d["init"], opts, out=out, host=host)
+        g = ctx.graph(d["data"], d["sizes"], d["offsets"], None if a.raw else d["init"], opts,
+                      out=out, host=host)
 
         def direct():
             d["data"].copy_(host["data"], non_blocking=True)
-            d["init"].copy_(host["init"], non_blocking=True)
-            ctx.fit_spots(d["data"], d["sizes"], d["offsets"], d["init"], opts, out=out)
+            if a.raw:
+                ctx.fit_raw(d["data"], d["sizes"], d["offsets"], opts, out=dict(out, init=d["init"]))
+            else:
+                d["init"].copy_(host["init"], non_blocking=True)
+                ctx.fit_spots(d["data"], d["sizes"], d["offsets"], d["init"], opts, out=out)
             for k in out:
                 host[k].copy_(out[k], non_blocking=True)
             torch.cuda.synchronize()
@@ -73,12 +82,14 @@ def main(argv=None):
             for i in range(a.frames):
                 f = frames[i % len(frames)]
                 host["data"].copy_(torch.from_numpy(f.data))
-                host["init"].copy_(torch.from_numpy(f.init))
+                if not a.raw:
+                    host["init"].copy_(torch.from_numpy(f.init))
                 t0 = time.perf_counter()
                 call()
                 ts.append(time.perf_counter() - t0)
             ts = np.asarray(ts[50:]) * 1e6
             print(json.dumps({"plan": plan, "mode": mode, "markers": n, "frames": len(ts),
+                              "start_values": "device" if a.raw else "host",
                               "p50_us": float(np.percentile(ts, 50)),
                               "p99_us": float(np.percentile(ts, 99)),
                               "mean_us": float(ts.mean())}), flush=True)

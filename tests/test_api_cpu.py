@@ -170,6 +170,15 @@ def test_graph_and_tracking_argument_errors():
     assert L.spotfit_graph_create(ctypes.byref(h), None, 1, 0, 1, 1, 1, 10, None, 1, 1, 1, 1,
                                   None) == -1
     assert h.value is None
+    fake = ctypes.c_void_p(0x10)
+    # a graph that computes its start values takes no host copy of them
+    io = sf.GraphIO(None, 0, 1, None, None, None, None)
+    assert L.spotfit_graph_create(ctypes.byref(h), fake, 1, 0, 1, 1, None, 10, None, 1, 1, 1, 1,
+                                  ctypes.byref(io)) == -2
+    # NULL outputs are still refused when init is NULL
+    assert L.spotfit_graph_create(ctypes.byref(h), fake, 1, 0, 1, 1, None, 10, None, None, 1, 1,
+                                  1, None) == -1
+    assert h.value is None
     assert L.spotfit_graph_launch(None, None) == -1
     L.spotfit_graph_destroy(None)
     assert L.spotfit_serve_track(None, 4, None, 8) == -1

@@ -103,3 +103,39 @@ def test_graph_mixed_schedule():
         for k in ("params", "chi2", "iters", "status"):
             np.testing.assert_array_equal(g.out[k].cpu().numpy(), want[k])
     g.close()
+
+
+@pytest.mark.parametrize("kw", [dict(max_side=13), dict(max_side=13, plan_hint=1),
+                                dict(schedule=1), dict(max_side=13, precision=0)],
+                         ids=["throughput", "latency", "mixed", "fp32"])
+def test_graph_of_raw_frames(kw):
+    """init None: every replay takes the pinned pixels of a frame to fits, start
+    values computed on the device; the bits of a direct fit_raw call."""
+    import torch
+
+    import paper_2106_02045_amd as sf
+    ctx = sf.Context(0)
+    _, _, frames = spotgen.drift_frames(5, n_markers=40, side=13, seed=33)
+    opts = sf.default_options(**kw)
+    f0 = frames[0]
+    n = f0.n
+    d = dict(data=_up(f0.data), sizes=_up(f0.sizes), offsets=_up(f0.offsets))
+    host = dict(data=torch.empty(f0.data.shape, dtype=torch.uint16).pin_memory(),
+                params=torch.empty((n, 6), dtype=torch.float32).pin_memory(),
+                chi2=torch.empty(n, dtype=torch.float32).pin_memory(),
+                iters=torch.empty(n, dtype=torch.int32).pin_memory(),
+                status=torch.empty(n, dtype=torch.int32).pin_memory())
+    g = ctx.graph(d["data"], d["sizes"], d["offsets"], None, opts, host=host)
+    for f in frames:
+        host["data"].copy_(torch.from_numpy(f.data))
+        for k in ("params", "chi2", "iters", "status"):
+            host[k].fill_(-1)
+        _eager_noise()
+        g.launch()
+        torch.cuda.synchronize()
+        want = ctx.fit_raw(_up(f.data), _up(f.sizes), _up(f.offsets), opts)
+        torch.cuda.synchronize()
+        for k in ("params", "chi2", "iters", "status"):
+            np.testing.assert_array_equal(host[k].numpy(), want[k].cpu().numpy())
+        assert np.all(host["status"].numpy() != sf.BAD_INPUT)
+    g.close()
