@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1000000,
                     help="spots of the same workload fitted by the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the oracle's timed run (default: the host's cores, at most 16)")
     ap.add_argument("--pmc-copy-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB once: the "
                          "calibration dispatch for hardware traffic counters")
@@ -194,7 +196,7 @@ def main():
         import oracle
         m = min(a.cpu_sample, n)
         sub = spotgen.workload(a.workload, n=m)
-        threads = min(os.cpu_count() or 1, 16)
+        threads = a.cpu_threads or min(os.cpu_count() or 1, 16)
         oo = oracle.default_opts(tie_tau=a.tie_tau)
         c0 = time.perf_counter()
         oracle.fit_batch(sub, oo, threads=threads)
