@@ -143,3 +143,26 @@ def test_fit_raw_zero_spots():
                       torch.zeros((0, 4), dtype=torch.uint8, device=dev),
                       torch.zeros(0, dtype=torch.int64, device=dev))
     assert out["init"].shape == (0, 4) and out["params"].shape == (0, 6)
+
+
+def test_fit_raw_full_size_scale_workload():
+    """1M spots of 15x15 in the benchmark's launch configuration: fit_raw gives
+    spotfit_moment_init's start values and fit_spots' results bit for bit on
+    every spot; a sample against the oracle's start values and fits."""
+    import paper_2106_02045_amd as sf
+    ctx = sf.Context(0)
+    b = spotgen.config(1, threads=16)
+    opts = sf.default_options(max_side=16)
+    raw, two, alone = _run(ctx, b, opts)
+    assert _same(raw["init"], alone)
+    for k in ("params", "chi2", "iters", "status", "evals"):
+        assert _same(raw[k], two[k]), k
+    assert np.all(raw["status"] != sf.BAD_INPUT)
+    idx = np.sort(np.random.default_rng(21).choice(b.n, size=3000, replace=False))
+    sub = b.subset(idx)
+    _check_init({"init": raw["init"][idx]}, sub, opts)
+    s2 = spotgen.SpotBatch(sub.data, sub.sizes, sub.offsets, raw["init"][idx], sub.truth, "fused")
+    r = oracle.fit_batch(s2, oracle.default_opts(), threads=8)
+    c = compare({k: v[idx] for k, v in raw.items()}, r, chi_band=1e-11, step_band=1e-9)
+    print(summary("fit_raw 1M sample", c))
+    assert c["strict_mismatch"] == 0 and c["tol_fail_same"] == 0
