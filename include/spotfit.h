@@ -173,7 +173,9 @@ int spotfit_ctx_reserve(spotfit_ctx_t* ctx, int64_t n_spots);
 
 /* Fit n_spots spots (see the layout above) on `stream`.  All array arguments
  * are device pointers; opt is a host pointer (NULL = defaults).  Allocates
- * nothing.  Returns SPOTFIT_OK or a negative spotfit_error_t. */
+ * nothing, except that a mixed-schedule call on more spots than the context has
+ * reserved grows its workspace first (spotfit_ctx_reserve).  Returns SPOTFIT_OK
+ * or a negative spotfit_error_t. */
 int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                       const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
                       int64_t n_spots, const spotfit_options_t* opt, float* params_out,

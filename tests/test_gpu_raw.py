@@ -75,6 +75,8 @@ CASES = [
     ("small_11x11", 3000, dict(max_side=8, plan_hint=1), False),
     ("precision_32x32_ell", 2000, dict(max_side=32, plan_hint=1), False),
     ("mixed_7to32", 6000, dict(precision=0), True),
+    ("scale_15x15", 3000, dict(max_side=16, precision=1), True),
+    ("small_11x11", 1000, dict(max_side=16, precision=3), True),
 ]
 
 
