@@ -89,17 +89,21 @@ struct spotfit_serve {
   std::vector<spotfit_ctx_t*> ctxs;
   std::vector<bool> stream_busy;
 
-  // rings: pixels (bytes) and per-spot records, device and pinned host mirrors
+  // rings indexed by spot position: pixels (bytes, device and pinned host
+  // mirror); per-spot records staged on the host as frames arrive (h_sizes,
+  // h_offs, h_init); a batch's records packed into its slice of the meta ring,
+  // kMetaBytes per spot (offsets, shapes, start values: one copy in), and its
+  // results into its slice of the result ring, kResBytes per spot (params, chi2,
+  // iterations, status: one copy out)
+  static constexpr int64_t kMetaBytes = 32, kResBytes = 36;
   int64_t pix_cap = 0, spot_cap = 0;
   unsigned char* d_pix = nullptr;
   unsigned char* h_pix = nullptr;
-  spotfit_shape_t *d_sizes = nullptr, *h_sizes = nullptr;
-  int64_t *d_offs = nullptr, *h_offs = nullptr;
-  float *d_init = nullptr, *h_init = nullptr;
-  float *d_params = nullptr, *h_params = nullptr;
-  float *d_chi2 = nullptr, *h_chi2 = nullptr;
-  int32_t *d_iters = nullptr, *h_iters = nullptr;
-  int32_t *d_status = nullptr, *h_status = nullptr;
+  spotfit_shape_t* h_sizes = nullptr;
+  int64_t* h_offs = nullptr;
+  float* h_init = nullptr;
+  unsigned char *d_meta = nullptr, *h_meta = nullptr;
+  unsigned char *d_res = nullptr, *h_res = nullptr;
   int64_t pix_head = 0, pix_used = 0, spot_head = 0, spot_used = 0;
 
   // frame slots, FIFO by ticket
@@ -156,6 +160,34 @@ hipError_t alloc_pair(T** d, T** h, int64_t n) {
   hipError_t e = hipMalloc((void**)d, sizeof(T) * (size_t)n);
   if (e != hipSuccess) return e;
   return hipHostMalloc((void**)h, sizeof(T) * (size_t)n, hipHostMallocDefault);
+}
+
+template <typename T>
+hipError_t alloc_host(T** h, int64_t n) {
+  return hipHostMalloc((void**)h, sizeof(T) * (size_t)n, hipHostMallocDefault);
+}
+
+// A batch of n spots in its slices of the meta and result rings.
+struct BatchView {
+  int64_t* offs;
+  spotfit_shape_t* sizes;
+  float* init;
+  float* params;
+  float* chi2;
+  int32_t* iters;
+  int32_t* status;
+};
+
+BatchView batch_view(unsigned char* meta, unsigned char* res, int64_t n) {
+  BatchView v;
+  v.offs = reinterpret_cast<int64_t*>(meta);
+  v.sizes = reinterpret_cast<spotfit_shape_t*>(meta + 8 * n);
+  v.init = reinterpret_cast<float*>(meta + 16 * n);
+  v.params = reinterpret_cast<float*>(res);
+  v.chi2 = reinterpret_cast<float*>(res + 24 * n);
+  v.iters = reinterpret_cast<int32_t*>(res + 28 * n);
+  v.status = reinterpret_cast<int32_t*>(res + 32 * n);
+  return v;
 }
 
 template <typename T>
@@ -236,37 +268,37 @@ bool spotfit_serve::launch_ready() {
       }
     }
   }
+  // the batch's records, packed on the host into its meta slice: one copy (the
+  // ring space of these spot positions is not in use by any other batch)
+  const BatchView hv = batch_view(h_meta + kMetaBytes * spot0, h_res + kResBytes * spot0, nsp);
+  const BatchView dv = batch_view(d_meta + kMetaBytes * spot0, d_res + kResBytes * spot0, nsp);
+  std::memcpy(hv.offs, h_offs + spot0, sizeof(int64_t) * nsp);
+  std::memcpy(hv.sizes, h_sizes + spot0, sizeof(spotfit_shape_t) * nsp);
+  if (!dev_init) std::memcpy(hv.init, h_init + 4 * spot0, sizeof(float) * 4 * nsp);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d_sizes + spot0, h_sizes + spot0, sizeof(spotfit_shape_t) * nsp,
+    e = hipMemcpyAsync(dv.offs, hv.offs, (size_t)(dev_init ? 12 : kMetaBytes) * nsp,
                        hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_offs + spot0, h_offs + spot0, sizeof(int64_t) * nsp, hipMemcpyHostToDevice, st);
   int rc = SPOTFIT_OK;
   if (e == hipSuccess && dev_init) {
     // start values on the device, in the fit's own launch
-    rc = spotfit_fit_raw(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0, nsp, &opt,
-                         d_init + 4 * spot0, d_params + 6 * spot0, d_chi2 + spot0, d_iters + spot0,
-                         d_status + spot0, nullptr, st);
+    rc = spotfit_fit_raw(ctxs[si], d_pix, dtype, dv.sizes, dv.offs, nsp, &opt, dv.init, dv.params,
+                         dv.chi2, dv.iters, dv.status, nullptr, st);
   } else if (e == hipSuccess) {
-    e = hipMemcpyAsync(d_init + 4 * spot0, h_init + 4 * spot0, sizeof(float) * 4 * nsp,
-                       hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, d_sizes + spot0, d_offs + spot0,
-                             d_init + 4 * spot0, nsp, &opt, d_params + 6 * spot0, d_chi2 + spot0,
-                             d_iters + spot0, d_status + spot0, nullptr, st);
+    rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, dv.sizes, dv.offs, dv.init, nsp, &opt,
+                           dv.params, dv.chi2, dv.iters, dv.status, nullptr, st);
   }
   int n_tracked = 0;
   if (e == hipSuccess && rc == SPOTFIT_OK && track_markers > 0) {
     sf::TrackFrame* tf = h_tf[si];
     for (uint64_t t = t0; t < t1; ++t) {
       const FrameRec& f = rec(t);
-      if (f.track_q >= 0) tf[n_tracked++] = sf::TrackFrame{f.spot0, f.track_q};
+      if (f.track_q >= 0) tf[n_tracked++] = sf::TrackFrame{f.spot0 - spot0, f.track_q};
     }
     if (n_tracked > 0) {
       e = hipMemcpyAsync(d_tf[si], tf, sizeof(sf::TrackFrame) * n_tracked, hipMemcpyHostToDevice, st);
       if (e == hipSuccess && track_ev_live) e = hipStreamWaitEvent(st, track_ev, 0);
       if (e == hipSuccess)
-        e = sf::launch_drift_track(d_tf[si], n_tracked, d_params, d_status, d_ref, track_markers,
+        e = sf::launch_drift_track(d_tf[si], n_tracked, dv.params, dv.status, d_ref, track_markers,
                                    d_hist, track_window, d_drift[si], st);
       if (e == hipSuccess) e = hipEventRecord(track_ev, st);
       track_ev_live = track_ev_live || e == hipSuccess;
@@ -276,14 +308,7 @@ bool spotfit_serve::launch_ready() {
     }
   }
   if (e == hipSuccess && rc == SPOTFIT_OK)
-    e = hipMemcpyAsync(h_params + 6 * spot0, d_params + 6 * spot0, sizeof(float) * 6 * nsp,
-                       hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess && rc == SPOTFIT_OK)
-    e = hipMemcpyAsync(h_chi2 + spot0, d_chi2 + spot0, sizeof(float) * nsp, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess && rc == SPOTFIT_OK)
-    e = hipMemcpyAsync(h_iters + spot0, d_iters + spot0, sizeof(int32_t) * nsp, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess && rc == SPOTFIT_OK)
-    e = hipMemcpyAsync(h_status + spot0, d_status + spot0, sizeof(int32_t) * nsp, hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(hv.params, dv.params, (size_t)kResBytes * nsp, hipMemcpyDeviceToHost, st);
   Batch b;
   b.stream = si;
   b.first_ticket = t0;
@@ -338,10 +363,13 @@ bool spotfit_serve::reap() {
           if (f.drift) *f.drift = h_drift[b.stream][tracked];
           ++tracked;
         }
-        std::memcpy(f.params, h_params + 6 * f.spot0, sizeof(float) * 6 * f.n);
-        std::memcpy(f.chi2, h_chi2 + f.spot0, sizeof(float) * f.n);
-        if (f.iters) std::memcpy(f.iters, h_iters + f.spot0, sizeof(int32_t) * f.n);
-        if (f.status) std::memcpy(f.status, h_status + f.spot0, sizeof(int32_t) * f.n);
+        const BatchView hv = batch_view(h_meta + kMetaBytes * b.spot0, h_res + kResBytes * b.spot0,
+                                        b.n_spots);
+        const int64_t rel = f.spot0 - b.spot0;
+        std::memcpy(f.params, hv.params + 6 * rel, sizeof(float) * 6 * f.n);
+        std::memcpy(f.chi2, hv.chi2 + rel, sizeof(float) * f.n);
+        if (f.iters) std::memcpy(f.iters, hv.iters + rel, sizeof(int32_t) * f.n);
+        if (f.status) std::memcpy(f.status, hv.status + rel, sizeof(int32_t) * f.n);
         f.state = kDone;
         ++frames_done;
         spots_done += (uint64_t)f.n;
@@ -473,9 +501,9 @@ int spotfit_serve_create(spotfit_serve_t** out, int device, const spotfit_option
   sv->n_streams = n_streams;
   sv->max_frames = max_frames;
   sv->frames.resize((size_t)max_frames);
-  // budget split: 3/4 pixels, 1/4 per-spot records (28 B in + 36 B out)
+  // budget split: 3/4 pixels, 1/4 per-spot records (32 B in + 36 B out)
   sv->pix_cap = (int64_t)(budget / 4 * 3) & ~(int64_t)255;
-  sv->spot_cap = (int64_t)(budget / 4) / 64;
+  sv->spot_cap = (int64_t)(budget / 4) / (spotfit_serve::kMetaBytes + spotfit_serve::kResBytes);
   hipError_t e = hipSetDevice(device);
   auto cleanup = [&](hipError_t err, const char* where) {
     spotfit_serve_destroy(sv);
@@ -483,13 +511,13 @@ int spotfit_serve_create(spotfit_serve_t** out, int device, const spotfit_option
   };
   if (e != hipSuccess) return cleanup(e, "hipSetDevice");
   if ((e = alloc_pair(&sv->d_pix, &sv->h_pix, sv->pix_cap)) != hipSuccess) return cleanup(e, "pixel ring");
-  if ((e = alloc_pair(&sv->d_sizes, &sv->h_sizes, sv->spot_cap)) != hipSuccess) return cleanup(e, "sizes ring");
-  if ((e = alloc_pair(&sv->d_offs, &sv->h_offs, sv->spot_cap)) != hipSuccess) return cleanup(e, "offsets ring");
-  if ((e = alloc_pair(&sv->d_init, &sv->h_init, 4 * sv->spot_cap)) != hipSuccess) return cleanup(e, "init ring");
-  if ((e = alloc_pair(&sv->d_params, &sv->h_params, 6 * sv->spot_cap)) != hipSuccess) return cleanup(e, "params ring");
-  if ((e = alloc_pair(&sv->d_chi2, &sv->h_chi2, sv->spot_cap)) != hipSuccess) return cleanup(e, "chi2 ring");
-  if ((e = alloc_pair(&sv->d_iters, &sv->h_iters, sv->spot_cap)) != hipSuccess) return cleanup(e, "iters ring");
-  if ((e = alloc_pair(&sv->d_status, &sv->h_status, sv->spot_cap)) != hipSuccess) return cleanup(e, "status ring");
+  if ((e = alloc_host(&sv->h_sizes, sv->spot_cap)) != hipSuccess) return cleanup(e, "sizes ring");
+  if ((e = alloc_host(&sv->h_offs, sv->spot_cap)) != hipSuccess) return cleanup(e, "offsets ring");
+  if ((e = alloc_host(&sv->h_init, 4 * sv->spot_cap)) != hipSuccess) return cleanup(e, "init ring");
+  if ((e = alloc_pair(&sv->d_meta, &sv->h_meta, spotfit_serve::kMetaBytes * sv->spot_cap)) != hipSuccess)
+    return cleanup(e, "record ring");
+  if ((e = alloc_pair(&sv->d_res, &sv->h_res, spotfit_serve::kResBytes * sv->spot_cap)) != hipSuccess)
+    return cleanup(e, "result ring");
   for (int i = 0; i < n_streams; ++i) {
     hipStream_t st = nullptr;
     if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return cleanup(e, "stream");
@@ -652,13 +680,11 @@ void spotfit_serve_destroy(spotfit_serve_t* sv) {
   for (auto c : sv->ctxs) spotfit_ctx_destroy(c);
   for (auto s : sv->streams) (void)hipStreamDestroy(s);
   free_pair(sv->d_pix, sv->h_pix);
-  free_pair(sv->d_sizes, sv->h_sizes);
-  free_pair(sv->d_offs, sv->h_offs);
-  free_pair(sv->d_init, sv->h_init);
-  free_pair(sv->d_params, sv->h_params);
-  free_pair(sv->d_chi2, sv->h_chi2);
-  free_pair(sv->d_iters, sv->h_iters);
-  free_pair(sv->d_status, sv->h_status);
+  free_pair<spotfit_shape_t>(nullptr, sv->h_sizes);
+  free_pair<int64_t>(nullptr, sv->h_offs);
+  free_pair<float>(nullptr, sv->h_init);
+  free_pair(sv->d_meta, sv->h_meta);
+  free_pair(sv->d_res, sv->h_res);
   delete sv;
 }
 
