@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 # Peak of this chip for single-lane FP32 / FP64 FMA: 256 CUs x 4 SIMD x 16 lanes
 # x 2 flop x 2.4 GHz.  (The 157.3 TFLOP/s FP32 figure needs packed FP32
-# instructions, which this build does not emit.)
+# instructions, which the library's kernels are compiled without.)
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBPS = 8000.0
 

@@ -146,12 +146,12 @@ _lib = None
 
 
 def lib():
-    """Load libspotfit.so (built by __graft_entry__.build()); raise if absent."""
+    """Load libspotfit.so (built by paper_2106_02045_amd/build.py); raise if absent."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise SpotfitError(f"{LIB_PATH} is missing: build the HIP library first "
-                               "(python -c 'import __graft_entry__ as g; g.build()')")
+                               "(python -m paper_2106_02045_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.spotfit_default_options.argtypes = [ctypes.POINTER(Options)]
