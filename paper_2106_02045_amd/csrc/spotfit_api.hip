@@ -309,6 +309,11 @@ int check_call(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   return SPOTFIT_OK;
 }
 
+// Largest batch for which the latency hint takes the one-wave-per-SIMD builds
+// of the wide plans (measured: faster up to 40,000 spots of the serving and
+// mixed workloads, slower from 400,000).
+constexpr int64_t kLeanMaxSpots = 65536;
+
 // Enqueue one fit with validated options o and n > 0.  init_out not NULL (with
 // init NULL): the separable double-precision kernels compute the start values
 // themselves and write them there.
@@ -350,8 +355,11 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
       if (rr != SPOTFIT_OK) return rr;
     }
     sf::MixedWs ws{ctx->ws, ctx->ws + 8, ctx->ws_cap};
-    // latency: the wide mixed-size plan (8, 16, 32 lanes per spot)
-    const int mplan = o.plan_hint == SPOTFIT_PLAN_LATENCY ? 0 : ctx->mixed_plan;
+    // latency: the wide mixed-size plan (8, 16, 32 lanes per spot); up to
+    // kLeanMaxSpots spots its one-wave-per-SIMD build, which spills no
+    // registers (those batches leave most of the chip idle anyway)
+    const int mplan = o.plan_hint == SPOTFIT_PLAN_LATENCY ? (n <= kLeanMaxSpots ? 3 : 0)
+                                                          : ctx->mixed_plan;
     const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_mixed[mplan];
     const int64_t need = (n + 1) / 2;
     const int grid = (int)(need < resident ? need : resident);

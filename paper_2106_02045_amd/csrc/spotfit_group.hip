@@ -729,13 +729,16 @@ hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t 
   return hipErrorInvalidValue;
 }
 
-// Mixed-size plans: plans of the classes (<= 8, <= 16, <= 32 px side).
+// Mixed-size plans: plans of the classes (<= 8, <= 16, <= 32 px side).  Plan 3
+// is plan 0 at one wave per SIMD: no register spills, for batches too small to
+// fill the chip (the latency hint's choice up to kLeanMaxSpots spots).
 #define SF_MIXED_PLANS(X)       \
   X(0, 8, 1, 16, 1, 32, 1, 3)   \
   X(1, 8, 1, 8, 2, 32, 1, 2)    \
-  X(2, 8, 1, 16, 1, 16, 2, 2)
+  X(2, 8, 1, 16, 1, 16, 2, 2)   \
+  X(3, 8, 1, 16, 1, 32, 1, 1)
 
-int wide_mixed_plan_count() { return 3; }
+int wide_mixed_plan_count() { return 4; }
 
 int mixed_plan_count() { return wide_mixed_plan_count() + narrow_mixed_plan_count(); }
 
