@@ -309,9 +309,9 @@ int check_call(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   return SPOTFIT_OK;
 }
 
-// Largest batch for which the latency hint takes the one-wave-per-SIMD builds
-// of the wide plans (measured: faster up to 40,000 spots of the serving and
-// mixed workloads, slower from 400,000).
+// Largest batch for which the latency hint takes the one-wave-per-SIMD build
+// of the wide mixed-size plan (measured: faster up to 40,000 spots of the
+// serving and mixed workloads, slower from 400,000).
 constexpr int64_t kLeanMaxSpots = 65536;
 
 // Enqueue one fit with validated options o and n > 0.  init_out not NULL (with
@@ -366,10 +366,19 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
     e = sf::launch_mixed(mplan, ka, ws, grid, (hipStream_t)stream);
   } else if (o.precision == SPOTFIT_PREC_FP64) {
     const int cls = o.max_side <= 8 ? 0 : o.max_side <= 16 ? 1 : 2;
-    // latency: the wide plans with one lane per column (8x1, 16x1, 32x1)
-    const int wide_for_class[3] = {0, 2, 4};
-    const int plan = o.plan_hint == SPOTFIT_PLAN_LATENCY ? wide_for_class[cls] : ctx->plan_for_class[cls];
+    // latency: the wide plans with one lane per column (8x1, 16x1, 32x1); the
+    // builds of 16x1 and 32x1 that spill no registers for batches that they hold
+    // resident at once (measured: up to 5-10 % faster there, 10-35 % slower at
+    // several resident rounds)
+    const int wide_for_class[3] = {0, 2, 4}, lean_for_class[3] = {0, 9, 10};
+    int plan = ctx->plan_for_class[cls];
     int lanes = 0, cpl = 0;
+    if (o.plan_hint == SPOTFIT_PLAN_LATENCY) {
+      plan = wide_for_class[cls];
+      const int lean = lean_for_class[cls];
+      sf::group_plan_shape(lean, &lanes, &cpl);
+      if (lean != plan && n <= (int64_t)ctx->n_cu * ctx->occ_plan[lean] * (64 / lanes)) plan = lean;
+    }
     sf::group_plan_shape(plan, &lanes, &cpl);
     const int64_t per_wave = 64 / lanes;
     const int64_t need = (n + per_wave - 1) / per_wave;

@@ -684,21 +684,33 @@ static const void* sym_lw() {
 }
 
 // The compiled plans: (lanes per spot, columns per lane, min waves per SIMD).
+// Entries 5 and 6 are entries 2 and 4 at one or two waves per SIMD, where they
+// spill no registers (for batches too small to fill the chip); they are plan
+// numbers 9 and 10, after the narrow plans 5..8.
 #define SF_GROUP_PLANS(X) \
   X(0, 8, 1, 2)           \
   X(1, 8, 2, 2)           \
   X(2, 16, 1, 3)          \
   X(3, 16, 2, 2)          \
-  X(4, 32, 1, 3)
+  X(4, 32, 1, 3)          \
+  X(5, 16, 1, 1)          \
+  X(6, 32, 1, 1)
 
 }  // namespace grp
 
 int wide_plan_count() { return 5; }
 
-int group_plan_count() { return wide_plan_count() + narrow_plan_count(); }
+int group_plan_count() { return wide_plan_count() + narrow_plan_count() + 2; }
+
+// Plan numbers: 0..4 wide, then the narrow plans, then the one-wave builds.
+static bool narrow_plan(int plan) {
+  return plan >= wide_plan_count() && plan < wide_plan_count() + narrow_plan_count();
+}
+static int wide_entry(int plan) { return plan < wide_plan_count() ? plan : plan - narrow_plan_count(); }
 
 void group_plan_shape(int plan, int* lanes, int* cpl) {
-  if (plan >= wide_plan_count()) return narrow_plan_shape(plan - wide_plan_count(), lanes, cpl);
+  if (narrow_plan(plan)) return narrow_plan_shape(plan - wide_plan_count(), lanes, cpl);
+  plan = wide_entry(plan);
 #define SF_SHAPE(I, L, C, W) \
   if (plan == I) {           \
     *lanes = L;              \
@@ -712,7 +724,8 @@ void group_plan_shape(int plan, int* lanes, int* cpl) {
 }
 
 const void* group_kernel_symbol(int plan) {
-  if (plan >= wide_plan_count()) return narrow_kernel_symbol(plan - wide_plan_count());
+  if (narrow_plan(plan)) return narrow_kernel_symbol(plan - wide_plan_count());
+  plan = wide_entry(plan);
 #define SF_SYM(I, L, C, W) \
   if (plan == I) return grp::sym_lw<L, C, W>();
   SF_GROUP_PLANS(SF_SYM)
@@ -721,7 +734,8 @@ const void* group_kernel_symbol(int plan) {
 }
 
 hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t st) {
-  if (plan >= wide_plan_count()) return launch_narrow_kernel(plan - wide_plan_count(), ka, grid, st);
+  if (narrow_plan(plan)) return launch_narrow_kernel(plan - wide_plan_count(), ka, grid, st);
+  plan = wide_entry(plan);
 #define SF_LAUNCH(I, L, C, W) \
   if (plan == I) return grp::launch_lw<L, C, W>(ka, grid, st);
   SF_GROUP_PLANS(SF_LAUNCH)

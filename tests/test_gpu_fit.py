@@ -168,8 +168,8 @@ def test_run_to_run_bitwise(gpu):
 # plan override (wide plans 0-4: lanes x columns 8x1, 8x2, 16x1, 16x2, 32x1;
 # narrow plans 5-8: 4x2, 4x4, 8x2, 16x2), reproduces the oracle's decisions.
 PLANS_UP_TO_8 = [0, 5]
-PLANS_UP_TO_16 = [1, 2, 3, 6, 7, 8]
-PLANS_UP_TO_32 = [4, 8]
+PLANS_UP_TO_16 = [1, 2, 3, 6, 7, 8, 9]
+PLANS_UP_TO_32 = [4, 8, 10]
 
 
 def _plan_fit(batch, cls, plan, side):
