@@ -320,7 +320,8 @@ constexpr int64_t kLeanMaxSpots = 65536;
 int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
                const int64_t* offsets, const float* init, int64_t n, const spotfit_options_t& o,
                float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
-               int32_t* evals_out, void* stream, float* init_out = nullptr) {
+               int32_t* evals_out, void* stream, float* init_out = nullptr,
+               const sf::MixedWs* classified = nullptr) {
   sf::KArgs ka;
   std::memset(&ka, 0, sizeof ka);
   ka.data = data;
@@ -350,11 +351,11 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
 
   hipError_t e;
   if (o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED) {
-    if (n > ctx->ws_cap) {
+    if (!classified && n > ctx->ws_cap) {
       const int rr = spotfit_ctx_reserve(ctx, n);
       if (rr != SPOTFIT_OK) return rr;
     }
-    sf::MixedWs ws{ctx->ws, ctx->ws + 8, ctx->ws_cap};
+    const sf::MixedWs ws = classified ? *classified : sf::MixedWs{ctx->ws, ctx->ws + 8, ctx->ws_cap};
     // latency: the wide mixed-size plan (8, 16, 32 lanes per spot); up to
     // kLeanMaxSpots spots its one-wave-per-SIMD build, which spills no
     // registers (those batches leave most of the chip idle anyway)
@@ -363,7 +364,8 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
     const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_mixed[mplan];
     const int64_t need = (n + 1) / 2;
     const int grid = (int)(need < resident ? need : resident);
-    e = sf::launch_mixed(mplan, ka, ws, grid, (hipStream_t)stream);
+    e = classified ? sf::launch_mixed_fit(mplan, ka, ws, grid, (hipStream_t)stream)
+                   : sf::launch_mixed(mplan, ka, ws, grid, (hipStream_t)stream);
   } else if (o.precision == SPOTFIT_PREC_FP64) {
     const int cls = o.max_side <= 8 ? 0 : o.max_side <= 16 ? 1 : 2;
     // latency: the wide plans with one lane per column (8x1, 16x1, 32x1); the
@@ -435,6 +437,22 @@ int launch_raw(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
 }
 
 }  // namespace
+
+namespace sf {
+
+int fit_preclassified(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                      const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
+                      float* init_out, int64_t n, const spotfit_options_t& o, const MixedWs& ws,
+                      float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
+                      void* stream) {
+  if (o.precision != SPOTFIT_PREC_FP64 || o.schedule != SPOTFIT_SCHEDULE_MIXED)
+    return fail(SPOTFIT_E_OPTIONS, "fit_preclassified: double precision, mixed schedule only");
+  if (n == 0) return SPOTFIT_OK;
+  return launch_fit(ctx, data, dtype, sizes, offsets, init_out ? nullptr : init, n, o, params_out,
+                    chi2_out, iters_out, status_out, nullptr, stream, init_out, &ws);
+}
+
+}  // namespace sf
 
 extern "C" {
 

@@ -780,6 +780,10 @@ hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, 
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
+  return launch_mixed_fit(plan, ka, ws, grid, st);
+}
+
+hipError_t launch_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid, hipStream_t st) {
   if (plan >= wide_mixed_plan_count())
     return launch_narrow_mixed_fit(plan - wide_mixed_plan_count(), ka, ws, grid, st);
 #define SF_MLAUNCH(I, A, B, C, D, E, F, W)                                                          \

@@ -63,6 +63,21 @@ struct MixedWs {
 int mixed_plan_count();
 const void* mixed_kernel_symbol(int plan);
 hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, hipStream_t st);
+// The fit of a mixed-size launch whose workspace already holds the class lists
+// and counts (taken counters zero), without the classify pass.
+hipError_t launch_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid, hipStream_t st);
+
+// A fit of spots whose size classes the caller listed (options validated,
+// double precision, mixed schedule): ws.counters[0..2] the class sizes,
+// ws.counters[3..5] zero, class c's spot indices at ws.lists + c * ws.cap, all
+// in device memory.  init_out not NULL: start values computed in the launch
+// and written there (init unused), as spotfit_fit_raw.  One launch, no
+// classify pass.  Returns SPOTFIT_OK or a negative spotfit_error_t.
+int fit_preclassified(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                      const spotfit_shape_t* sizes, const int64_t* offsets, const float* init,
+                      float* init_out, int64_t n, const spotfit_options_t& o, const MixedWs& ws,
+                      float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
+                      void* stream);
 
 // Plans of the separable kernel: plan p groups `lanes` lanes per spot with `cpl`
 // columns per lane and holds spots with w, h <= lanes * cpl.  Plans below

@@ -57,7 +57,8 @@ struct FrameRec {
   int64_t spot0 = 0;       // first index in the spot ring
   int64_t pix_off = 0;     // byte offset in the pixel ring
   int64_t pix_bytes = 0;   // bytes reserved in the pixel ring (incl. skipped tail)
-  int64_t pix_alloc = 0;   // aligned bytes of the frame's own pixels
+  int64_t pix_alloc = 0;   // aligned bytes of the frame's pixels and records
+  int64_t meta_off = 0;    // byte offset in the pixel ring of the frame's records
   int64_t spot_res = 0;    // spots reserved in the spot ring (incl. skipped tail)
   uint64_t t_arrival = 0;  // ns
   uint64_t t_done = 0;
@@ -167,6 +168,34 @@ hipError_t alloc_host(T** h, int64_t n) {
   return hipHostMalloc((void**)h, sizeof(T) * (size_t)n, hipHostMallocDefault);
 }
 
+// A frame's own records, staged right after its pixels in the pixel ring so that
+// a batch of one frame moves them in with its pixels: offsets (8 B per spot),
+// shapes (4 B), start values (16 B, after 4 B of padding), the size-class lists
+// (3 x 4 B: class c's spot indices from c * n) and the eight counters of a
+// mixed-size launch (class sizes, then zeros).
+int64_t frame_meta_bytes(int64_t n) { return n > 0 ? (44 * n + 32 + 255) & ~(int64_t)255 : 0; }
+
+struct FrameMeta {
+  int64_t* offs;
+  spotfit_shape_t* sizes;
+  float* init;
+  int32_t* lists;
+  int32_t* counters;
+};
+
+FrameMeta frame_meta(unsigned char* m, int64_t n) {
+  return FrameMeta{reinterpret_cast<int64_t*>(m), reinterpret_cast<spotfit_shape_t*>(m + 8 * n),
+                   reinterpret_cast<float*>(m + 16 * n), reinterpret_cast<int32_t*>(m + 32 * n),
+                   reinterpret_cast<int32_t*>(m + 44 * n)};
+}
+
+// Size class of a spot in a mixed-size launch (largest side <= 8, <= 16, <= 32),
+// as the device's classify pass assigns it.
+int size_class_of(const spotfit_shape_t& sh) {
+  const int m = sh.w > sh.h ? sh.w : sh.h;
+  return m <= 8 ? 0 : m <= 16 ? 1 : 2;
+}
+
 // A batch of n spots in its slices of the meta and result rings.
 struct BatchView {
   int64_t* offs;
@@ -268,24 +297,34 @@ bool spotfit_serve::launch_ready() {
       }
     }
   }
-  // the batch's records, packed on the host into its meta slice: one copy (the
-  // ring space of these spot positions is not in use by any other batch)
   const BatchView hv = batch_view(h_meta + kMetaBytes * spot0, h_res + kResBytes * spot0, nsp);
   const BatchView dv = batch_view(d_meta + kMetaBytes * spot0, d_res + kResBytes * spot0, nsp);
-  std::memcpy(hv.offs, h_offs + spot0, sizeof(int64_t) * nsp);
-  std::memcpy(hv.sizes, h_sizes + spot0, sizeof(spotfit_shape_t) * nsp);
-  if (!dev_init) std::memcpy(hv.init, h_init + 4 * spot0, sizeof(float) * 4 * nsp);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dv.offs, hv.offs, (size_t)(dev_init ? 12 : kMetaBytes) * nsp,
-                       hipMemcpyHostToDevice, st);
   int rc = SPOTFIT_OK;
-  if (e == hipSuccess && dev_init) {
-    // start values on the device, in the fit's own launch
-    rc = spotfit_fit_raw(ctxs[si], d_pix, dtype, dv.sizes, dv.offs, nsp, &opt, dv.init, dv.params,
-                         dv.chi2, dv.iters, dv.status, nullptr, st);
-  } else if (e == hipSuccess) {
-    rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, dv.sizes, dv.offs, dv.init, nsp, &opt,
+  if (t1 == t0 + 1 && opt.precision == SPOTFIT_PREC_FP64 && opt.schedule == SPOTFIT_SCHEDULE_MIXED) {
+    // one frame: its records and class lists came in with its pixels, and the
+    // fit starts without a classify pass: two API calls fewer per frame, which
+    // the dispatcher thread otherwise spends while the GPU waits
+    const FrameMeta m = frame_meta(d_pix + rec(t0).meta_off, nsp);
+    const sf::MixedWs ws{m.counters, m.lists, nsp};
+    if (e == hipSuccess)
+      rc = sf::fit_preclassified(ctxs[si], d_pix, dtype, m.sizes, m.offs, dev_init ? nullptr : m.init,
+                                 dev_init ? m.init : nullptr, nsp, opt, ws, dv.params, dv.chi2,
+                                 dv.iters, dv.status, st);
+  } else {
+    // the batch's records, packed on the host into its meta slice: one copy (the
+    // ring space of these spot positions is not in use by any other batch)
+    std::memcpy(hv.offs, h_offs + spot0, sizeof(int64_t) * nsp);
+    std::memcpy(hv.sizes, h_sizes + spot0, sizeof(spotfit_shape_t) * nsp);
+    if (!dev_init) std::memcpy(hv.init, h_init + 4 * spot0, sizeof(float) * 4 * nsp);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dv.offs, hv.offs, (size_t)(dev_init ? 12 : kMetaBytes) * nsp,
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && dev_init)  // start values on the device, in the fit's own launch
+      rc = spotfit_fit_raw(ctxs[si], d_pix, dtype, dv.sizes, dv.offs, nsp, &opt, dv.init,
                            dv.params, dv.chi2, dv.iters, dv.status, nullptr, st);
+    else if (e == hipSuccess)
+      rc = spotfit_fit_spots(ctxs[si], d_pix, dtype, dv.sizes, dv.offs, dv.init, nsp, &opt,
+                             dv.params, dv.chi2, dv.iters, dv.status, nullptr, st);
   }
   int n_tracked = 0;
   if (e == hipSuccess && rc == SPOTFIT_OK && track_markers > 0) {
@@ -557,7 +596,8 @@ int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_
   const int64_t esz = fr->dtype == SPOTFIT_U16 ? 2 : 4;
   int64_t npx = 0;
   for (int64_t i = 0; i < n; ++i) npx += (int64_t)fr->sizes[i].w * fr->sizes[i].h;
-  const int64_t bytes = ((npx * esz) + 255) & ~(int64_t)255;
+  const int64_t px_bytes = ((npx * esz) + 255) & ~(int64_t)255;
+  const int64_t bytes = px_bytes + frame_meta_bytes(n);
   std::unique_lock<std::mutex> lk(sv->mu);
   if (fr->drift_out && (sv->track_markers == 0 || n != sv->track_markers))
     return serve_fail(SPOTFIT_E_ARG, "serve_submit: a tracked frame needs tracking on and one spot per marker");
@@ -585,6 +625,7 @@ int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_
   f.pix_off = sv->pix_head;
   f.pix_bytes = bytes + pix_skip;
   f.pix_alloc = bytes;
+  f.meta_off = f.pix_off + px_bytes;
   f.spot_res = n + spot_skip;
   f.t_arrival = arrival_ns ? arrival_ns : now_ns();
   f.params = fr->params_out;
@@ -607,6 +648,20 @@ int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* fr, uint64_
   for (int64_t i = 0; i < n; ++i) {
     sv->h_offs[f.spot0 + i] = o;
     o += (int64_t)fr->sizes[i].w * fr->sizes[i].h;
+  }
+  if (n > 0) {
+    // the frame's own records after its pixels (a batch of this frame alone
+    // reads them from there)
+    const FrameMeta m = frame_meta(sv->h_pix + f.meta_off, n);
+    std::memcpy(m.offs, sv->h_offs + f.spot0, sizeof(int64_t) * n);
+    std::memcpy(m.sizes, fr->sizes, sizeof(spotfit_shape_t) * n);
+    if (fr->init) std::memcpy(m.init, fr->init, sizeof(float) * 4 * n);
+    int32_t cnt[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+      const int c = size_class_of(fr->sizes[i]);
+      m.lists[c * n + cnt[c]++] = (int32_t)i;
+    }
+    for (int c = 0; c < 8; ++c) m.counters[c] = c < 3 ? cnt[c] : 0;
   }
   if (sv->t_first == 0) sv->t_first = f.t_arrival;
   sv->next_ticket = t + 1;
