@@ -368,7 +368,9 @@ typedef struct {
 
 /* Create a serving loop on `device` with fit options `opt` (NULL = defaults):
  * device memory for at most `device_mem_budget` bytes of frames in flight
- * (3/4 pixels, 1/4 per-spot records, plus pinned host mirrors of the same size),
+ * (3/4 pixels, each frame's pixels followed by its own records, 44 bytes per
+ * spot; 1/4 per-spot records of batches, 68 bytes per spot; plus pinned host
+ * mirrors of the same size),
  * at most `max_frames` frames in flight, `n_streams` streams (each with its own
  * context) so that batches overlap on the device.  Starts a dispatcher thread. */
 int spotfit_serve_create(spotfit_serve_t** sv, int device, const spotfit_options_t* opt,
