@@ -50,7 +50,23 @@ class Result(ctypes.Structure):
         ("n_trial", ctypes.c_int32),
         ("margin_chi", ctypes.c_double),
         ("margin_step", ctypes.c_double),
+        ("min_pivot", ctypes.c_double),
     ]
+
+
+class Event(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("iter", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("p", ctypes.c_double * 4),
+        ("delta", ctypes.c_double * 4),
+        ("chi", ctypes.c_double),
+    ]
+
+
+EV_GRAD, EV_TRIAL, EV_RETRY = range(3)
 
 
 def build(force: bool = False) -> str:
@@ -73,34 +89,43 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.orc_default_opts.argtypes = [ctypes.POINTER(Opts)]
-        L.orc_eval.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
-                               dp, dp, dp, dp]
-        L.orc_eval.restype = ctypes.c_int
-        L.orc_solve.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, dp]
-        L.orc_solve.restype = ctypes.c_int
-        L.orc_pow10.argtypes = [ctypes.c_int]
-        L.orc_pow10.restype = ctypes.c_double
-        L.orc_fit_spot.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                   ctypes.POINTER(ctypes.c_float), ctypes.POINTER(Opts),
-                                   ctypes.POINTER(Result)]
-        vp = ctypes.c_void_p
-        L.orc_fit_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int64,
-                                    ctypes.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp,
-                                    ctypes.c_int]
-        L.orc_fit_batch.restype = ctypes.c_int
-        L.orc_moment_init.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
-        L.orc_moment_init.restype = ctypes.c_int
-        L.orc_moment_init_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp]
-        L.orc_moment_init_batch.restype = ctypes.c_int
-        L.orc_peak_init.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
-        L.orc_peak_init.restype = ctypes.c_int
-        L.orc_peak_init_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp]
-        L.orc_peak_init_batch.restype = ctypes.c_int
-        _lib = L
+        _lib = bind(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def bind(L):
+    """Declare the argument and return types of the oracle's functions on a loaded
+    library (this one, or a copy built from edited sources by a test)."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.orc_eval.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
+                           dp, dp, dp, dp]
+    L.orc_eval.restype = ctypes.c_int
+    L.orc_solve.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, dp]
+    L.orc_solve.restype = ctypes.c_int
+    L.orc_pow10.argtypes = [ctypes.c_int]
+    L.orc_pow10.restype = ctypes.c_double
+    L.orc_fit_spot.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_float), ctypes.POINTER(Opts),
+                               ctypes.POINTER(Result)]
+    L.orc_fit_spot_traced.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_float), ctypes.POINTER(Opts),
+                                      ctypes.POINTER(Result), ctypes.POINTER(Event),
+                                      ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    vp = ctypes.c_void_p
+    L.orc_fit_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int64,
+                                ctypes.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                ctypes.c_int]
+    L.orc_fit_batch.restype = ctypes.c_int
+    L.orc_moment_init.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    L.orc_moment_init.restype = ctypes.c_int
+    L.orc_moment_init_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp]
+    L.orc_moment_init_batch.restype = ctypes.c_int
+    L.orc_peak_init.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
+    L.orc_peak_init.restype = ctypes.c_int
+    L.orc_peak_init_batch.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int64, vp]
+    L.orc_peak_init_batch.restype = ctypes.c_int
+    return L
 
 
 def default_opts(**kw) -> Opts:
@@ -157,7 +182,31 @@ def fit_spot(g, w: int, h: int, model: int, init4, opts: Optional[Opts] = None) 
                        ctypes.byref(o), ctypes.byref(r))
     return dict(params=np.array(r.params[:]), chi2=r.chi2, iters=r.iters, status=r.status,
                 n_grad=r.n_grad, n_trial=r.n_trial, margin_chi=r.margin_chi,
-                margin_step=r.margin_step)
+                margin_step=r.margin_step, min_pivot=r.min_pivot)
+
+
+def fit_spot_traced(g, w: int, h: int, model: int, init4, opts: Optional[Opts] = None,
+                    cap: int = 2048):
+    """fit_spot plus the loop's trajectory: (result dict, list of event dicts with
+    kind (EV_GRAD / EV_TRIAL / EV_RETRY), iter, k, p, delta, chi)."""
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(-1))
+    init4 = np.ascontiguousarray(np.asarray(init4, dtype=np.float32).reshape(4))
+    o = opts if opts is not None else default_opts()
+    r = Result()
+    ev = (Event * cap)()
+    n_ev = ctypes.c_int(0)
+    lib().orc_fit_spot_traced(_dp(g), w, h, model,
+                              init4.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                              ctypes.byref(o), ctypes.byref(r), ev, cap, ctypes.byref(n_ev))
+    if n_ev.value > cap:
+        raise RuntimeError(f"trajectory of {n_ev.value} events exceeds cap {cap}")
+    n = nparams(model)
+    events = [dict(kind=e.kind, iter=e.iter, k=e.k, p=np.array(e.p[:n]),
+                   delta=np.array(e.delta[:n]), chi=e.chi) for e in ev[:n_ev.value]]
+    res = dict(params=np.array(r.params[:]), chi2=r.chi2, iters=r.iters, status=r.status,
+               n_grad=r.n_grad, n_trial=r.n_trial, margin_chi=r.margin_chi,
+               margin_step=r.margin_step, min_pivot=r.min_pivot)
+    return res, events
 
 
 def fit_batch(batch, opts: Optional[Opts] = None, threads: int = 1) -> dict:
@@ -176,14 +225,16 @@ def fit_batch(batch, opts: Optional[Opts] = None, threads: int = 1) -> dict:
     init = np.ascontiguousarray(batch.init, dtype=np.float32)
     out = dict(params=np.zeros((n, 6)), chi2=np.zeros(n), iters=np.zeros(n, np.int32),
                status=np.zeros(n, np.int32), n_grad=np.zeros(n, np.int32),
-               n_trial=np.zeros(n, np.int32), margin_chi=np.zeros(n), margin_step=np.zeros(n))
+               n_trial=np.zeros(n, np.int32), margin_chi=np.zeros(n), margin_step=np.zeros(n),
+               min_pivot=np.zeros(n))
     if n == 0:
         return out
     rc = lib().orc_fit_batch(data.ctypes.data, dtype, sizes.ctypes.data, offs.ctypes.data,
                              init.ctypes.data, n, ctypes.byref(o),
                              *(out[k].ctypes.data for k in ("params", "chi2", "iters", "status",
                                                             "n_grad", "n_trial", "margin_chi",
-                                                            "margin_step")), int(threads))
+                                                            "margin_step", "min_pivot")),
+                             int(threads))
     if rc != 0:
         raise RuntimeError(f"orc_fit_batch failed ({rc})")
     return out

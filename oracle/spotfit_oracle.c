@@ -176,7 +176,13 @@ int orc_eval(const double* g, int w, int h, int model, const double* p, int want
   return 0;
 }
 
-int orc_solve(const double* A, const double* bvec, int n, double lam, double* delta) {
+/* Cholesky solve of the damped system; *min_pivot (when not NULL) is lowered to
+ * the smallest ratio of a pivot to its diagonal entry, s_j / M_jj in (0, 1]: how
+ * much of each diagonal entry survives elimination.  Its reciprocal grows like
+ * the condition number of the diagonally scaled matrix, which sets how far
+ * rounding in A and b can move delta. */
+static int chol_solve(const double* A, const double* bvec, int n, double lam, double* delta,
+                      double* min_pivot) {
   double M[ORC_MAXP][ORC_MAXP], L[ORC_MAXP][ORC_MAXP], y[ORC_MAXP];
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) M[i][j] = A[i * n + j] + (i == j ? lam * A[i * n + j] : 0.0);
@@ -185,6 +191,7 @@ int orc_solve(const double* A, const double* bvec, int n, double lam, double* de
     double s = M[j][j];
     for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
     if (!(s > 0.0) || !isfinite(s)) goto fail;
+    if (min_pivot && M[j][j] > 0.0 && s / M[j][j] < *min_pivot) *min_pivot = s / M[j][j];
     L[j][j] = sqrt(s);
     for (int i = j + 1; i < n; ++i) {
       double t = M[i][j];
@@ -208,6 +215,10 @@ int orc_solve(const double* A, const double* bvec, int n, double lam, double* de
 fail:
   for (int i = 0; i < n; ++i) delta[i] = NAN;
   return 1;
+}
+
+int orc_solve(const double* A, const double* bvec, int n, double lam, double* delta) {
+  return chol_solve(A, bvec, n, lam, delta, NULL);
 }
 
 static double clampnan(double v, double lo, double hi) {
@@ -243,13 +254,41 @@ static int all_small(const double* d, const double* best, int n, double rel, dou
   return all;
 }
 
+/* Appends one evaluation of the loop to the trajectory log (when one is kept). */
+static void log_eval(orc_event* ev, int cap, int* n_ev, int kind, int iter, int k,
+                     const double* p, const double* delta, double chi, int n) {
+  if (!ev || !n_ev || *n_ev >= cap) {
+    if (n_ev) ++*n_ev;
+    return;
+  }
+  orc_event* e = &ev[*n_ev];
+  memset(e, 0, sizeof *e);
+  e->kind = kind;
+  e->iter = iter;
+  e->k = k;
+  for (int j = 0; j < n; ++j) {
+    e->p[j] = p[j];
+    e->delta[j] = delta ? delta[j] : 0.0;
+  }
+  e->chi = chi;
+  ++*n_ev;
+}
+
 void orc_fit_spot(const double* g, int w, int h, int model, const float* init4,
                   const orc_opts* o, orc_result* res) {
+  orc_fit_spot_traced(g, w, h, model, init4, o, res, NULL, 0, NULL);
+}
+
+void orc_fit_spot_traced(const double* g, int w, int h, int model, const float* init4,
+                         const orc_opts* o, orc_result* res, orc_event* ev, int cap,
+                         int* n_ev) {
   const int n = orc_nparams(model);
+  if (n_ev) *n_ev = 0;
   const int N = w * h;
   memset(res, 0, sizeof *res);
   res->margin_chi = INFINITY;
   res->margin_step = INFINITY;
+  res->min_pivot = 1.0;
   for (int i = 0; i < 6; ++i) res->params[i] = NAN;
   res->chi2 = NAN;
   res->status = ORC_BAD_INPUT;
@@ -277,16 +316,18 @@ void orc_fit_spot(const double* g, int w, int h, int model, const float* init4,
     orc_eval(g, w, h, model, p, 1, e3, A, bvec, NULL);
     res->n_grad++;
     double chi = e3[2];
+    log_eval(ev, cap, n_ev, ORC_EV_GRAD, it, k, p, NULL, chi, n);
     if (isnan(chi)) { status = ORC_NOT_CONVERGED; break; }
     if (chi_below(chi, T, T, mc)) { status = ORC_MAX_ERROR; break; }
 
     memcpy(best, p, sizeof(double) * n);
-    orc_solve(A, bvec, n, orc_pow10(k), delta);
+    chol_solve(A, bvec, n, orc_pow10(k), delta, &res->min_pivot);
     for (int j = 0; j < n; ++j) p[j] = best[j] + delta[j];
     limit_params(p, model, w, h, o);
     orc_eval(g, w, h, model, p, 0, e3, NULL, NULL, NULL);
     res->n_trial++;
     double Chi = e3[2];
+    log_eval(ev, cap, n_ev, ORC_EV_TRIAL, it, k, p, delta, Chi, n);
 
     /* improved: Chi < chi(1 - tau) -> less damping */
     if (chi_below(Chi, chi * (1.0 - tau), chi, mc)) --k;
@@ -296,12 +337,13 @@ void orc_fit_spot(const double* g, int w, int h, int model, const float* init4,
     while (!all_small(delta, best, n, o->min_step_rel, ms) &&
            chi_below(chi * (1.0 + tau), Chi, chi, mc) && k < o->lambda_max_exp10) {
       ++k;
-      orc_solve(A, bvec, n, orc_pow10(k), delta);
+      chol_solve(A, bvec, n, orc_pow10(k), delta, &res->min_pivot);
       for (int j = 0; j < n; ++j) p[j] = best[j] + delta[j];
       limit_params(p, model, w, h, o);
       orc_eval(g, w, h, model, p, 0, e3, NULL, NULL, NULL);
       res->n_trial++;
       Chi = e3[2];
+      log_eval(ev, cap, n_ev, ORC_EV_RETRY, it, k, p, delta, Chi, n);
     }
 
     if (chi_below(chi * (1.0 + tau), Chi, chi, mc) || isnan(Chi)) {
@@ -331,6 +373,7 @@ typedef struct {
   const void* data; int dtype; const uint8_t* sizes; const int64_t* offsets; const float* init;
   const orc_opts* o; double* params; double* chi2; int32_t* iters; int32_t* status;
   int32_t* n_grad; int32_t* n_trial; double* margin_chi; double* margin_step;
+  double* min_pivot;
   int64_t lo, hi;
 } orc_job;
 
@@ -359,6 +402,7 @@ static void* run_job(void* arg) {
     if (jb->n_trial) jb->n_trial[s] = r.n_trial;
     if (jb->margin_chi) jb->margin_chi[s] = r.margin_chi;
     if (jb->margin_step) jb->margin_step[s] = r.margin_step;
+    if (jb->min_pivot) jb->min_pivot[s] = r.min_pivot;
   }
   return NULL;
 }
@@ -366,7 +410,8 @@ static void* run_job(void* arg) {
 int orc_fit_batch(const void* data, int dtype, const uint8_t* sizes, const int64_t* offsets,
                   const float* init, int64_t n, const orc_opts* o, double* params,
                   double* chi2, int32_t* iters, int32_t* status, int32_t* n_grad,
-                  int32_t* n_trial, double* margin_chi, double* margin_step, int n_threads) {
+                  int32_t* n_trial, double* margin_chi, double* margin_step,
+                  double* min_pivot, int n_threads) {
   if (n < 0 || (dtype != 0 && dtype != 1) || !o) return -1;
   if (n == 0) return 0;
   if (!data || !sizes || !offsets || !init || !params || !chi2 || !iters || !status) return -1;
@@ -381,7 +426,7 @@ int orc_fit_batch(const void* data, int dtype, const uint8_t* sizes, const int64
     jb->data = data; jb->dtype = dtype; jb->sizes = sizes; jb->offsets = offsets;
     jb->init = init; jb->o = o; jb->params = params; jb->chi2 = chi2; jb->iters = iters;
     jb->status = status; jb->n_grad = n_grad; jb->n_trial = n_trial;
-    jb->margin_chi = margin_chi; jb->margin_step = margin_step;
+    jb->margin_chi = margin_chi; jb->margin_step = margin_step; jb->min_pivot = min_pivot;
     jb->lo = t * per;
     jb->hi = (t + 1) * per < n ? (t + 1) * per : n;
   }

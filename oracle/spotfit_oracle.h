@@ -14,7 +14,13 @@
  *   orc_solve  pinned to a generic dense solve of the damped system (Eq. 14).
  *   orc_fit_*  pinned by noise-free recovery, by equality with an explicit
  *              five-parameter least-squares fit (scipy), by brute-force grid
- *              search on tiny spots, and statistically by Table 1 / Fig. 8.
+ *              search on tiny spots, statistically by Table 1 / Fig. 8, and
+ *              in its control flow by replaying the logged trajectory
+ *              (orc_fit_spot_traced) against the pseudo-code with chi^2, the
+ *              Jacobian and the damped step computed independently in the
+ *              tests, through every exit: the damping cap with the best point
+ *              restored, MaxError before and after a trial, MinDelta, MinStep,
+ *              and the iteration budget.
  *   The status codes, the MaxError threshold "A/3", the limit() box and the
  *   chi^2 normalisation are the paper's unspecified details: parity unpinned.
  *   orc_moment_init  (start values, outside the paper's method) pinned by
@@ -59,6 +65,8 @@ typedef struct {
   int32_t n_trial;     /* evaluations without derivatives (trial steps)               */
   double  margin_chi;  /* smallest relative margin of any chi^2 comparison taken       */
   double  margin_step; /* smallest relative margin of any step-size comparison taken   */
+  double  min_pivot;   /* smallest pivot / diagonal ratio of any damped solve (1 = none;
+                          near 0: an ill-conditioned step that rounding can move far)  */
 } orc_result;
 
 void orc_default_opts(orc_opts* o);
@@ -86,13 +94,35 @@ double orc_pow10(int k);
 void orc_fit_spot(const double* g, int w, int h, int model, const float* init4,
                   const orc_opts* o, orc_result* res);
 
+/* One evaluation of the Levenberg-Marquardt loop, in the order the loop takes
+ * them: the evaluation with derivatives that opens iteration `iter` (GRAD), the
+ * first trial of that iteration (TRIAL) and each retry with more damping
+ * (RETRY).  k is the damping exponent in force (for a trial: the one its step
+ * was solved with), p the point evaluated (a trial's is limit(best + delta)),
+ * delta the unclamped step of a trial (0 for GRAD), chi its chi^2 (NaN when
+ * the evaluation failed). */
+enum { ORC_EV_GRAD = 0, ORC_EV_TRIAL = 1, ORC_EV_RETRY = 2 };
+typedef struct {
+  int32_t kind, iter, k, pad;
+  double  p[4];
+  double  delta[4];
+  double  chi;
+} orc_event;
+
+/* orc_fit_spot that also logs its trajectory: up to cap events into ev, their
+ * total count (which may exceed cap) into *n_ev.  ev may be NULL. */
+void orc_fit_spot_traced(const double* g, int w, int h, int model, const float* init4,
+                         const orc_opts* o, orc_result* res, orc_event* ev, int cap,
+                         int* n_ev);
+
 /* Batch driver over the ragged layout; dtype 0 = uint16, 1 = float32.
  * Every output array has n entries (params: n*6).  Spots are split into
  * contiguous static chunks over n_threads POSIX threads. Returns 0 or -1. */
 int orc_fit_batch(const void* data, int dtype, const uint8_t* sizes, const int64_t* offsets,
                   const float* init, int64_t n, const orc_opts* o, double* params,
                   double* chi2, int32_t* iters, int32_t* status, int32_t* n_grad,
-                  int32_t* n_trial, double* margin_chi, double* margin_step, int n_threads);
+                  int32_t* n_trial, double* margin_chi, double* margin_step,
+                  double* min_pivot, int n_threads);
 
 /* Centroid / second-moment start values of one spot (row-major g, w x h):
  * background = median of the border ring, weights max(g - b0, 0), weighted

@@ -116,7 +116,22 @@ MIXED_SIDES = np.array([7, 9, 11, 15, 21, 25, 32])
 
 def _law_mixed(rng, m):
     # side U{7,9,11,15,21,25,32}; half symmetric, half elliptical; sigma U[1,3]
-    # per axis; amplitude, background and noise laws of the 32x32 workload.
+    # per axis; amplitude, background and noise laws of the 15x15 workload
+    # (alpha log-uniform [1e2,1e4], beta U[10,200], Poisson plus read noise sd 2).
+    side = MIXED_SIDES[rng.integers(0, len(MIXED_SIDES), size=m)]
+    model = rng.integers(0, 2, size=m)
+    off = rng.uniform(-1.0, 1.0, size=(m, 2))
+    sig = rng.uniform(1.0, 3.0, size=(m, 2))
+    sig[model == SYM, 1] = sig[model == SYM, 0]
+    alpha = 10.0 ** rng.uniform(2.0, 4.0, size=m)
+    beta = rng.uniform(10.0, 200.0, size=m)
+    return side, side, model, off, sig, alpha, beta, 2.0
+
+
+def _law_mixed_low(rng, m):
+    # the mixed sizes and models with the low-contrast laws of the 32x32 workload
+    # (alpha U[50,300], beta U[200,1000], Poisson): dim spots whose trials are
+    # often worse, for tests of the damping retries and their cap.
     side = MIXED_SIDES[rng.integers(0, len(MIXED_SIDES), size=m)]
     model = rng.integers(0, 2, size=m)
     off = rng.uniform(-1.0, 1.0, size=(m, 2))
@@ -150,6 +165,7 @@ WORKLOADS = {
     "precision_32x32_ell": (_law_precision, 1_000_000, 2),
     "mixed_7to32": (_law_mixed, 2_000_000, 3),
     "serve_fiducials": (_law_serve, 0, 4),
+    "mixed_low_contrast": (_law_mixed_low, 20000, 5),
 }
 CONFIG_NAMES = ["small_11x11", "scale_15x15", "precision_32x32_ell", "mixed_7to32",
                 "serve_fiducials"]

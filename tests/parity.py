@@ -5,8 +5,12 @@ relative chi^2 < 1e-5; identical status and iteration count.  A spot whose
 oracle trajectory passes a decision closer than the kernel's chi^2 error to its
 threshold ("knife-edge": the oracle logs the smallest relative margin of every
 chi^2 comparison and every step-size comparison it makes) may legitimately take
-the other branch; such spots are counted and reported, and must still satisfy
-the parameter tolerances when they end with the same status.
+the other branch; so may a spot whose trajectory passes an ill-conditioned
+damped solve (the oracle logs the smallest ratio of a Cholesky pivot to its
+diagonal entry: below pivot_band, rounding in the normal equations moves the
+step by more than the decisions can absorb).  Such spots are counted and
+reported, and must still satisfy the parameter tolerances when they end with
+the same status and are not ill-conditioned.
 """
 from __future__ import annotations
 
@@ -22,7 +26,8 @@ def _rel(a, b):
         return np.abs(a / b - 1.0)
 
 
-def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None) -> dict:
+def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None,
+            pivot_band: float = 0.0) -> dict:
     """g: GPU outputs (params [n,6] f32, chi2, iters, status); r: oracle.fit_batch dict."""
     gp = np.asarray(g["params"], dtype=np.float64)
     rp = r["params"]
@@ -45,6 +50,8 @@ def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None) -> 
     same_status = g["status"] == r["status"]
     same_iters = g["iters"] == r["iters"]
     knife = (r["margin_chi"] < chi_band) | (r["margin_step"] < step_band)
+    ill = r["min_pivot"] < pivot_band if "min_pivot" in r else np.zeros(n, bool)
+    knife = knife | ill
     in_tol = (dxy < TOL_XY) & (relmax < TOL_REL) & (rchi < TOL_CHI)
     in_tol = np.where(bad_in, True, in_tol)
     # BAD_INPUT: status must match and outputs must be NaN on both sides
@@ -59,17 +66,35 @@ def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None) -> 
         strict_mismatch=int((strict & ~same).sum()),
         tol_fail_same=int((same & ~in_tol).sum()),
         tol_fail_any=int((~in_tol).sum()),
+        tol_fail_strict=int((~knife & ~in_tol).sum()),
+        n_ill=int(ill.sum()),
         max_dxy=float(np.nanmax(np.where(bad_in, 0, dxy))) if n else 0.0,
         max_rel=float(np.nanmax(np.where(bad_in, 0, relmax))) if n else 0.0,
         max_rchi=float(np.nanmax(np.where(bad_in, 0, rchi))) if n else 0.0,
         med_rchi=float(np.nanmedian(rchi[~bad_in])) if (~bad_in).any() else 0.0,
         bad_input_nan=bool(nan_ok),
         mismatch_idx=np.nonzero(~same)[0],
+        fail_idx=np.nonzero((strict & ~same) | (~knife & ~in_tol))[0],
     )
 
 
+def describe(g: dict, r: dict, idx, limit: int = 8) -> str:
+    """Both sides' results for the listed spots (for failure messages)."""
+    lines = []
+    for s in list(idx)[:limit]:
+        lines.append(
+            f"spot {s}: gpu status {int(g['status'][s])} iters {int(g['iters'][s])} "
+            f"params {np.round(np.asarray(g['params'][s], np.float64), 6).tolist()} | oracle "
+            f"status {int(r['status'][s])} iters {int(r['iters'][s])} "
+            f"params {np.round(r['params'][s], 6).tolist()} margins chi "
+            f"{r['margin_chi'][s]:.2e} step {r['margin_step'][s]:.2e} pivot "
+            f"{r.get('min_pivot', np.ones(len(r['status'])))[s]:.2e}")
+    return "\n".join(lines)
+
+
 def summary(name: str, c: dict) -> str:
-    return (f"{name}: n={c['n']} knife={c['n_knife']} status_mis={c['status_mismatch']} "
+    return (f"{name}: n={c['n']} knife={c['n_knife']} (ill-conditioned {c['n_ill']}) "
+            f"status_mis={c['status_mismatch']} "
             f"iters_mis={c['iters_mismatch']} strict_mis={c['strict_mismatch']} "
             f"tol_fail(same)={c['tol_fail_same']} tol_fail(any)={c['tol_fail_any']} "
             f"max|dxy|={c['max_dxy']:.2e} max_rel={c['max_rel']:.2e} "

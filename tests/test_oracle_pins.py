@@ -335,6 +335,256 @@ def test_fig8_iteration_and_stop_statistics():
 
 
 # ---------------------------------------------------------------------------
+# The loop's control flow (Levenberg-Marquardt section, Fit2DGaussian
+# pseudo-code), pinned by replaying the oracle's logged trajectory with numbers
+# computed here independently: chi^2 from numpy's least-squares solve of g on
+# [f, 1], the normal equations from a central-difference Jacobian of that
+# residual, the damped step from numpy.linalg.solve.  The replay takes each
+# decision the pseudo-code prescribes and checks that the oracle took the same
+# one, evaluation by evaluation, through to the returned point and status.
+# ---------------------------------------------------------------------------
+
+_DEFAULTS = dict(max_iter=20, max_error_per_px=1.0 / 3.0, min_delta=1e-6, min_step_rel=1e-4,
+                 lambda0_exp10=-2, lambda_max_exp10=4, sigma_min=0.3, sigma_max_frac=1.0)
+
+
+def _chi2_lstsq(g, w, h, model, p):
+    r, coef = _lstsq_residual(g, w, h, model, p)
+    return float(r @ r), coef
+
+
+def _residual_complex(g, w, h, model, p):
+    """h - g at complex shaping parameters: the 2x2 normal equations of (alpha,
+    beta) solved by numpy's generic solver (analytic in p, no conjugation)."""
+    x, y = _grid_xy(w, h)
+    if model == 0:
+        f = np.exp(-((x - p[0]) ** 2 + (y - p[1]) ** 2) / (2 * p[2] ** 2))
+    else:
+        f = np.exp(-(x - p[0]) ** 2 / (2 * p[2] ** 2) - (y - p[1]) ** 2 / (2 * p[3] ** 2))
+    M = np.array([[np.sum(f * f), np.sum(f)], [np.sum(f), float(w * h)]])
+    coef = np.linalg.solve(M, np.array([np.sum(f * g), np.sum(g)]))
+    return coef[0] * f + coef[1] - g
+
+
+def _normal_fd(g, w, h, model, p):
+    """J^T J and J^T (g - h), J = d(h - g)/dp by complex-step differentiation of the
+    residual (derivative to rounding accuracy, independent of Eqs. 7-9)."""
+    n = len(p)
+    J = np.zeros((w * h, n))
+    for j in range(n):
+        pc = p.astype(np.complex128)
+        pc[j] += 1e-30j
+        J[:, j] = _residual_complex(g, w, h, model, pc).imag / 1e-30
+    r, _ = _lstsq_residual(g, w, h, model, p)
+    return J.T @ J, -J.T @ r
+
+
+def _replay(g, w, h, model, init, kw, res, events):
+    """Walk the pseudo-code with independent numbers; returns the exit branch."""
+    o = dict(_DEFAULTS, **kw)
+    n = 3 if model == 0 else 4
+    T = o["max_error_per_px"] * w * h
+    smax = o["sigma_max_frac"] * max(w, h)
+
+    def limit(q):
+        q = q.copy()
+        q[0] = min(max(q[0], -0.5), w - 0.5)
+        q[1] = min(max(q[1], -0.5), h - 0.5)
+        q[2:] = np.minimum(np.maximum(q[2:], o["sigma_min"]), smax)
+        return q
+
+    pos = 0
+
+    def take(kind, it, k, p, d=None):
+        """Check the oracle's next evaluation against the replay's; continue from the
+        oracle's point (equal to the replay's up to rounding) so that rounding
+        differences do not accumulate; chi^2 there by lstsq."""
+        nonlocal pos
+        assert pos < len(events), "the oracle stopped early"
+        e = events[pos]
+        pos += 1
+        assert (e["kind"], e["iter"], e["k"]) == (kind, it, k), (e, kind, it, k)
+        np.testing.assert_allclose(e["p"], p, rtol=1e-7, atol=1e-8)
+        if d is not None:
+            np.testing.assert_allclose(e["delta"], d, rtol=1e-7,
+                                       atol=1e-9 * np.abs(d).max() + 1e-13)
+        q = np.array(e["p"], dtype=np.float64)
+        chi, _ = _chi2_lstsq(g, w, h, model, q)
+        assert e["chi"] == pytest.approx(chi, rel=1e-10)
+        return q, chi
+
+    def solve(A, b, k):
+        return np.linalg.solve(A + 10.0 ** k * np.diag(np.diag(A)), b)
+
+    p = np.asarray(init, dtype=np.float32).astype(np.float64)[:n]
+    k, it, status, branch = o["lambda0_exp10"], 0, oracle.MAX_ITER, "max_iter"
+    retried = False
+    while it < o["max_iter"]:
+        it += 1
+        p, chi = take(oracle.EV_GRAD, it, k, p)
+        A, b = _normal_fd(g, w, h, model, p)
+        if chi < T:
+            status, branch = oracle.MAX_ERROR, "maxerr_grad"
+            break
+        best = p.copy()
+        d = solve(A, b, k)
+        p, Chi = take(oracle.EV_TRIAL, it, k, limit(best + d), d)
+        if Chi < chi:
+            k -= 1
+        small = bool(np.all(np.abs(d) < o["min_step_rel"] * np.abs(best)))
+        while not small and Chi > chi and k < o["lambda_max_exp10"]:
+            k += 1
+            retried = True
+            d = solve(A, b, k)
+            p, Chi = take(oracle.EV_RETRY, it, k, limit(best + d), d)
+            small = bool(np.all(np.abs(d) < o["min_step_rel"] * np.abs(best)))
+        if Chi > chi:
+            p = best
+            status = oracle.NOT_CONVERGED
+            branch = "cap" if (not small and k >= o["lambda_max_exp10"]) else "nc_small_step"
+            break
+        if Chi < T:
+            status, branch = oracle.MAX_ERROR, "maxerr_trial"
+            break
+        if chi * (1 - o["min_delta"]) < Chi:
+            status, branch = oracle.MIN_DELTA, "min_delta"
+            break
+        if small:
+            status, branch = oracle.MIN_STEP, "min_step"
+            break
+    assert pos == len(events), "the oracle evaluated more than the pseudo-code prescribes"
+    assert (res["status"], res["iters"]) == (status, it)
+    np.testing.assert_allclose(res["params"][:n] if model else res["params"][:3], p,
+                               rtol=1e-7, atol=1e-8)
+    chi_end, coef = _chi2_lstsq(g, w, h, model, p)
+    assert res["chi2"] == pytest.approx(chi_end, rel=1e-9)
+    np.testing.assert_allclose(res["params"][4:6], coef, rtol=1e-8, atol=1e-8)
+    return branch + ("+retry" if retried and branch != "cap" else "")
+
+
+def _replay_cases():
+    """(batch, option overrides, spots per exit branch) with every exit of the loop."""
+    return [
+        (spotgen.workload("mixed_low_contrast", n=2500), dict(lambda0_exp10=-8,
+                                                             lambda_max_exp10=-5), 12),
+        (spotgen.paper_protocol(1500, 4, 400, 40), dict(lambda_max_exp10=-2), 12),
+        (spotgen.paper_protocol(1500, 4, 400, 40), dict(), 8),
+        (spotgen.config(0, n=400), dict(max_error_per_px=230.0), 8),
+        (spotgen.noise_free(120), dict(), 6),
+        (spotgen.config(1, n=300), dict(), 6),
+        (spotgen.paper_protocol(800, 7, 160, 49), dict(), 6),
+    ]
+
+
+def _replay_batch(batch, kw, per_branch, fit=None):
+    fit = fit or oracle.fit_spot_traced
+    o = oracle.default_opts(**kw)
+    seen = {}
+    for s in range(batch.n):
+        w, h, m = (int(v) for v in batch.sizes[s, :3])
+        g = batch.spot(s).astype(np.float64).ravel()
+        res, ev = fit(g, w, h, m, batch.init[s], o)
+        # decisions closer to their threshold than the two sides' rounding can
+        # resolve are left out
+        if res["margin_chi"] < 1e-9 or res["margin_step"] < 1e-6:
+            continue
+        key = res["status"], len(ev) > 0 and ev[-1]["kind"], \
+            any(e["kind"] == oracle.EV_RETRY for e in ev)
+        if seen.get(key, 0) >= per_branch:
+            continue
+        seen[key] = seen.get(key, 0) + 1
+        yield _replay(g, w, h, m, batch.init[s], kw, res, ev)
+
+
+def test_loop_trajectory_replays_the_pseudo_code():
+    """Every exit of the loop, each reached by the oracle on these inputs: the
+    damping cap with the best point restored (NotConverged), MaxError before and
+    after a trial, MinDelta and MinStep with and without retries, and an
+    exhausted iteration budget."""
+    branches = {}
+    for batch, kw, per in _replay_cases():
+        for br in _replay_batch(batch, kw, per):
+            branches[br] = branches.get(br, 0) + 1
+    print(branches)
+    for want in ("cap", "maxerr_grad", "maxerr_trial", "min_delta", "min_delta+retry",
+                 "min_step", "max_iter"):
+        assert branches.get(want, 0) > 0, (want, branches)
+
+
+def test_no_retry_when_the_cap_is_the_start_damping():
+    """lambda_max = lambda0: a first trial that is worse ends the fit at iteration 1
+    with NotConverged and the start point, with no retry (checked against chi^2
+    computed here)."""
+    b = spotgen.paper_protocol(600, 4, 400, 40)
+    o = oracle.default_opts(lambda_max_exp10=-2)
+    hits = 0
+    for s in range(b.n):
+        g = b.spot(s).astype(np.float64).ravel()
+        p0 = b.init[s].astype(np.float64)[:3]
+        chi0, _ = _chi2_lstsq(g, 4, 4, 0, p0)
+        A, bv = _normal_fd(g, 4, 4, 0, p0)
+        d = np.linalg.solve(A + 1e-2 * np.diag(np.diag(A)), bv)
+        p1 = p0 + d
+        p1[:2] = np.clip(p1[:2], -0.5, 3.5)
+        p1[2] = np.clip(p1[2], 0.3, 4.0)
+        chi1, _ = _chi2_lstsq(g, 4, 4, 0, p1)
+        if not chi1 > chi0 * (1 + 1e-9):
+            continue
+        hits += 1
+        r = oracle.fit_spot(g, 4, 4, 0, b.init[s], o)
+        assert r["status"] == oracle.NOT_CONVERGED and r["iters"] == 1
+        assert r["n_trial"] == 1
+        np.testing.assert_array_equal(r["params"][:3], p0)
+    assert hits >= 10
+
+
+_MISTAKES = {
+    # one retry too many: the damping may exceed the cap
+    "retry_past_cap": ("k < o->lambda_max_exp10", "k <= o->lambda_max_exp10"),
+    # NotConverged without restoring the best point
+    "no_restore": ("memcpy(p, best, sizeof(double) * n);\n      status = ORC_NOT_CONVERGED;",
+                   "status = ORC_NOT_CONVERGED;"),
+    # MaxError tested on the error before the step instead of the trial's
+    "maxerr_on_chi": ("if (chi_below(Chi, T, T, mc)) { status = ORC_MAX_ERROR; break; }",
+                      "if (chi_below(chi, T, T, mc)) { status = ORC_MAX_ERROR; break; }"),
+    # the damping not reduced after an improving first trial
+    "no_decrease": ("if (chi_below(Chi, chi * (1.0 - tau), chi, mc)) --k;",
+                    "if (chi_below(Chi, chi * (1.0 - tau), chi, mc)) k = k;"),
+}
+
+
+@pytest.mark.parametrize("mistake", list(_MISTAKES))
+def test_replay_catches_planted_loop_mistakes(tmp_path, mistake):
+    """A copy of the oracle with one control-flow mistake planted fails the replay."""
+    import ctypes
+    import subprocess
+    src = open(oracle.SRC_PATH).read()
+    old, new = _MISTAKES[mistake]
+    assert src.count(old) >= 1, mistake
+    c = tmp_path / "mutant.c"
+    c.write_text(src.replace(old, new))
+    so = tmp_path / "mutant.so"
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-std=gnu99", "-ffp-contract=off",
+                    "-I", os.path.dirname(oracle.SRC_PATH), "-o", str(so), str(c), "-lm",
+                    "-lpthread"], check=True)
+    mutant = oracle.bind(ctypes.CDLL(str(so)))
+    saved = oracle._lib
+    oracle._lib = mutant
+    try:
+        caught = False
+        for batch, kw, per in _replay_cases():
+            try:
+                for _ in _replay_batch(batch, kw, per):
+                    pass
+            except AssertionError:
+                caught = True
+                break
+        assert caught, f"planted mistake {mistake} passed the replay"
+    finally:
+        oracle._lib = saved
+
+
+# ---------------------------------------------------------------------------
 # Start values (centroid / second moments): outside the paper's method, pinned
 # by hand-built images whose estimate is known exactly.
 # ---------------------------------------------------------------------------
