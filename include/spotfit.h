@@ -307,9 +307,11 @@ typedef struct {
  * same from frame to frame: the caller refills the inputs (device arrays, or
  * the pinned host buffers of io) and replays the whole call with one
  * spotfit_graph_launch.  The capture runs on a private stream and launches
- * nothing; the mixed schedule's workspace is reserved beforehand.  Replays use
- * the context's buffers: do not overlap them with other calls on the same
- * context.  init may be NULL: the graph then computes the start values on
+ * nothing.  The mixed schedule's workspace (12 bytes per spot plus 32) belongs
+ * to the graph: allocated here, freed in spotfit_graph_destroy, so later calls
+ * on the context (which may grow the context's own workspace) leave it alone.
+ * Replays use the context's spot counter: do not overlap them with other calls
+ * on the same context.  init may be NULL: the graph then computes the start values on
  * the device as spotfit_fit_raw does (inside the fit's launch for the
  * double-precision kernels), into a buffer of n x 4 floats it allocates here
  * and frees in spotfit_graph_destroy, so that a replay takes raw pixels to
@@ -401,7 +403,12 @@ int spotfit_serve_track(spotfit_serve_t* sv, int32_t n_markers, const float* ref
 int spotfit_serve_submit(spotfit_serve_t* sv, const spotfit_frame_t* frame, uint64_t arrival_ns,
                          uint64_t* ticket);
 
-/* 0 when the frame's results are in its arrays, 1 while pending, < 0 on error. */
+/* 0 when the frame's results are in its arrays, 1 while pending, < 0 on error:
+ * SPOTFIT_E_HIP for a frame whose batch failed (its arrays are not written),
+ * for as long as the server lives, also after its ring space is reused.  For
+ * tests of this handling, the environment variable SPOTFIT_SERVE_FAIL_BATCH=k
+ * read by spotfit_serve_create makes the k-th batch fail on the host, before
+ * anything of it is enqueued. */
 int spotfit_serve_poll(spotfit_serve_t* sv, uint64_t ticket);
 /* Block until the frame is done; SPOTFIT_OK or < 0 on error. */
 int spotfit_serve_wait(spotfit_serve_t* sv, uint64_t ticket);

@@ -552,10 +552,22 @@ class Server:
         whose drift record lands in outputs["drift"] (a structured array of one)."""
         import numpy as np
         data = np.ascontiguousarray(data)
-        sizes = np.ascontiguousarray(sizes, dtype=np.uint8)
-        if init is not None:
-            init = np.ascontiguousarray(init, dtype=np.float32)
+        if data.dtype not in (np.uint16, np.float32):
+            raise TypeError(f"frame data must be uint16 or float32, got {data.dtype}")
+        sizes = np.asarray(sizes)
+        if sizes.dtype != np.uint8 or sizes.ndim != 2 or sizes.shape[1] != 4:
+            raise TypeError("frame sizes must be a uint8 array of shape [n, 4]")
+        sizes = np.ascontiguousarray(sizes)
         n = int(sizes.shape[0])
+        npx = int((sizes[:, 0].astype(np.int64) * sizes[:, 1].astype(np.int64)).sum())
+        if data.ndim != 1 or data.size < npx:
+            raise ValueError(f"frame data must be flat and hold the {npx} pixels its sizes name, "
+                             f"got shape {data.shape}")
+        if init is not None:
+            init = np.asarray(init)
+            if init.dtype != np.float32 or init.shape != (n, 4):
+                raise TypeError(f"frame init must be float32 of shape ({n}, 4)")
+            init = np.ascontiguousarray(init)
         outs = dict(params=np.zeros((n, 6), np.float32), chi2=np.zeros(n, np.float32),
                     iters=np.zeros(n, np.int32), status=np.zeros(n, np.int32))
         if track:
@@ -581,9 +593,12 @@ class Server:
         return t.value, outs
 
     def wait(self, ticket: int):
+        """Block until the frame is done; its outputs, or SpotfitError if it failed."""
         rc = lib().spotfit_serve_wait(self._h, int(ticket))
         if rc != 0:
-            raise SpotfitError(f"spotfit_serve_wait failed with {rc}")
+            self._keep.pop(ticket, None)
+            raise SpotfitError(f"spotfit_serve_wait failed with {rc}: "
+                               f"{lib().spotfit_serve_last_error().decode(errors='replace')}")
         return self._keep.pop(ticket)
 
     def poll(self, ticket: int) -> int:

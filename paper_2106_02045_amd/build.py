@@ -1,12 +1,19 @@
-"""Build libspotfit.so in-tree with hipcc for gfx950."""
+"""Build libspotfit.so in-tree with hipcc for gfx950.
+
+Each source compiles to its own object in parallel (every kernel is launched
+from the file that defines it, so no relocatable device code is needed), then
+one link makes the shared library.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 SOURCES = ["spotfit_kernels.hip", "spotfit_group.hip", "spotfit_narrow.hip", "spotfit_init.hip",
            "spotfit_plain.hip", "spotfit_api.hip",
            "spotfit_serve.hip", "spotfit_track.hip"]
@@ -14,24 +21,35 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 OUT = os.path.join(HERE, "libspotfit.so")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     # single-lane FP32 arithmetic only: no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+NOISE = "is not a recognized feature for this target"
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "is not a recognized feature for this target"
-    err = "\n".join(l for l in (r.stderr or "").splitlines() if noise not in l)
+    err = "\n".join(l for l in (r.stderr or "").splitlines() if NOISE not in l)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + err)
-    if verbose and err.strip():
-        print(err)
+    return err
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    objs = [os.path.join(OBJ, s.replace(".hip", ".o")) for s in SOURCES]
+    cmds = [[HIPCC, *FLAGS, "-c", "-o", o, os.path.join(CSRC, s)] for s, o in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(jobs) as ex:
+        errs = list(ex.map(_run, cmds))
+    tmp = OUT + ".tmp"
+    errs.append(_run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]))
+    if verbose:
+        for e in errs:
+            if e.strip():
+                print(e)
     os.replace(tmp, OUT)
     return OUT
 

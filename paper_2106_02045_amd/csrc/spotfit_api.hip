@@ -316,12 +316,15 @@ constexpr int64_t kLeanMaxSpots = 65536;
 
 // Enqueue one fit with validated options o and n > 0.  init_out not NULL (with
 // init NULL): the separable double-precision kernels compute the start values
-// themselves and write them there.
+// themselves and write them there.  Mixed schedule: `classified` is a
+// workspace whose class lists are already built (no classify pass); otherwise
+// `own_ws` (not NULL: a workspace of at least n spots that the caller owns) or
+// the context's workspace, grown to n spots if needed, takes the classify pass.
 int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
                const int64_t* offsets, const float* init, int64_t n, const spotfit_options_t& o,
                float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
                int32_t* evals_out, void* stream, float* init_out = nullptr,
-               const sf::MixedWs* classified = nullptr) {
+               const sf::MixedWs* classified = nullptr, const sf::MixedWs* own_ws = nullptr) {
   sf::KArgs ka;
   std::memset(&ka, 0, sizeof ka);
   ka.data = data;
@@ -351,11 +354,13 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
 
   hipError_t e;
   if (o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED) {
-    if (!classified && n > ctx->ws_cap) {
+    if (!classified && !own_ws && n > ctx->ws_cap) {
       const int rr = spotfit_ctx_reserve(ctx, n);
       if (rr != SPOTFIT_OK) return rr;
     }
-    const sf::MixedWs ws = classified ? *classified : sf::MixedWs{ctx->ws, ctx->ws + 8, ctx->ws_cap};
+    const sf::MixedWs ws = classified ? *classified
+                           : own_ws   ? *own_ws
+                                      : sf::MixedWs{ctx->ws, ctx->ws + 8, ctx->ws_cap};
     // latency: the wide mixed-size plan (8, 16, 32 lanes per spot); up to
     // kLeanMaxSpots spots its one-wave-per-SIMD build, which spills no
     // registers (those batches leave most of the chip idle anyway)
@@ -424,16 +429,16 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
 int launch_raw(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
                const int64_t* offsets, int64_t n, const spotfit_options_t& o, float* init_out,
                float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
-               int32_t* evals_out, void* stream) {
+               int32_t* evals_out, void* stream, const sf::MixedWs* own_ws = nullptr) {
   if (o.precision == SPOTFIT_PREC_FP64)
     return launch_fit(ctx, data, dtype, sizes, offsets, nullptr, n, o, params_out, chi2_out,
-                      iters_out, status_out, evals_out, stream, init_out);
+                      iters_out, status_out, evals_out, stream, init_out, nullptr, own_ws);
   const hipError_t e = sf::launch_start_values(sf::kInitMoments, data, dtype, sizes, offsets, n,
                                                o.max_side, o.max_pixels, init_out,
                                                (hipStream_t)stream);
   if (e != hipSuccess) return fail_hip(e, "start-value kernel launch");
   return launch_fit(ctx, data, dtype, sizes, offsets, init_out, n, o, params_out, chi2_out,
-                    iters_out, status_out, evals_out, stream);
+                    iters_out, status_out, evals_out, stream, nullptr, nullptr, own_ws);
 }
 
 }  // namespace
@@ -646,6 +651,8 @@ struct spotfit_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   float* init_buf = nullptr;  // start values of a graph that computes them (init NULL)
+  int32_t* ws = nullptr;      // the mixed schedule's workspace, owned by the graph (its
+                              // kernels keep this address for every replay)
 };
 
 extern "C" {
@@ -677,14 +684,23 @@ int spotfit_graph_create(spotfit_graph_t** out, spotfit_ctx_t* ctx, const void* 
   hipError_t e = hipGetDevice(&guard.prev);
   if (e == hipSuccess) e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
-  // the mixed schedule's workspace is sized before the capture: nothing allocates inside it
-  if (o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED && n > ctx->ws_cap) {
-    rc = spotfit_ctx_reserve(ctx, n);
-    if (rc != SPOTFIT_OK) return rc;
-  }
   spotfit_graph* g = new (std::nothrow) spotfit_graph();
   if (!g) return fail(SPOTFIT_E_ARG, "graph_create: out of host memory");
   g->device = ctx->device;
+  // the mixed schedule's workspace belongs to the graph and is allocated before the
+  // capture: nothing allocates inside it, and a later call that grows the
+  // context's workspace cannot free memory the replays use
+  const bool mixed = o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED;
+  sf::MixedWs gws{nullptr, nullptr, 0};
+  if (mixed) {
+    e = hipMalloc((void**)&g->ws, sizeof(int32_t) * (size_t)(8 + 3 * n));
+    if (e != hipSuccess) {
+      g->ws = nullptr;
+      spotfit_graph_destroy(g);
+      return fail_hip(e, "hipMalloc (graph workspace)");
+    }
+    gws = sf::MixedWs{g->ws, g->ws + 8, n};
+  }
   if (raw) {
     e = hipMalloc((void**)&g->init_buf, sizeof(float) * 4 * (size_t)n);
     if (e != hipSuccess) {
@@ -709,10 +725,10 @@ int spotfit_graph_create(spotfit_graph_t** out, spotfit_ctx_t* ctx, const void* 
   rc = SPOTFIT_OK;
   if (e == hipSuccess && raw)
     rc = launch_raw(ctx, data, dtype, sizes, offsets, n, o, g->init_buf, params_out, chi2_out,
-                    iters_out, status_out, nullptr, st);
+                    iters_out, status_out, nullptr, st, mixed ? &gws : nullptr);
   else if (e == hipSuccess)
     rc = launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
-                    status_out, nullptr, st);
+                    status_out, nullptr, st, nullptr, nullptr, mixed ? &gws : nullptr);
   if (e == hipSuccess && rc == SPOTFIT_OK && io && io->params)
     e = hipMemcpyAsync(io->params, params_out, sizeof(float) * 6 * (size_t)n, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && rc == SPOTFIT_OK && io && io->chi2)
@@ -748,6 +764,7 @@ void spotfit_graph_destroy(spotfit_graph_t* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   if (g->init_buf) (void)hipFree(g->init_buf);
+  if (g->ws) (void)hipFree(g->ws);
   delete g;
 }
 

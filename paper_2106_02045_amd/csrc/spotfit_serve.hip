@@ -24,12 +24,14 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
 #include <new>
 #include <string>
 #include <thread>
+#include <unordered_set>
 #include <vector>
 
 #include "spotfit.h"
@@ -133,6 +135,13 @@ struct spotfit_serve {
   std::vector<spotfit_drift_t*> h_drift, d_drift;
   hipEvent_t track_ev = nullptr;  // the last launched drift pass
   bool track_ev_live = false;
+
+  // failed frames keep their failure after their ring space is released
+  std::unordered_set<uint64_t> failed_tickets;
+  // failure handling test hook: batch number fail_batch (1-based; 0 = never)
+  // fails on the host without enqueueing anything
+  int64_t fail_batch = 0;
+  int64_t batches_started = 0;
 
   // statistics
   std::vector<uint64_t> lat_ns;
@@ -274,10 +283,11 @@ bool spotfit_serve::launch_ready() {
     stream_busy[si] = true;
   }
   hipStream_t st = streams[si];
+  const bool injected = fail_batch > 0 && ++batches_started == fail_batch;
   // pixel bytes of the batch: frames are consecutive in the pixel ring except
   // where it wrapped, so copy maximal contiguous runs
-  hipError_t e = hipSuccess;
-  {
+  hipError_t e = injected ? hipErrorUnknown : hipSuccess;
+  if (!injected) {
     int64_t run0 = -1, run1 = -1;
     for (uint64_t t = t0; t <= t1 && e == hipSuccess; ++t) {
       const bool last = t == t1;
@@ -369,7 +379,9 @@ bool spotfit_serve::launch_ready() {
   }
   std::lock_guard<std::mutex> lk(mu);
   if (b.failed && error.empty())
-    error = std::string("serve batch failed: ") + (rc != SPOTFIT_OK ? spotfit_last_error() : hipGetErrorString(e));
+    error = injected ? std::string("serve batch failed: injected failure (test hook)")
+                     : std::string("serve batch failed: ") +
+                           (rc != SPOTFIT_OK ? spotfit_last_error() : hipGetErrorString(e));
   inflight.push_back(b);
   ++batches;
   return true;
@@ -414,6 +426,7 @@ bool spotfit_serve::reap() {
         spots_done += (uint64_t)f.n;
       } else {
         f.state = kFailed;
+        failed_tickets.insert(f.ticket);
         ++frames_failed;
       }
       f.t_done = tnow;
@@ -537,6 +550,7 @@ int spotfit_serve_create(spotfit_serve_t** out, int device, const spotfit_option
   if (!sv) return serve_fail(SPOTFIT_E_ARG, "serve_create: out of host memory");
   sv->device = device;
   sv->opt = o;
+  if (const char* env = std::getenv("SPOTFIT_SERVE_FAIL_BATCH")) sv->fail_batch = std::atoll(env);
   sv->n_streams = n_streams;
   sv->max_frames = max_frames;
   sv->frames.resize((size_t)max_frames);
@@ -680,7 +694,8 @@ int spotfit_serve_poll(spotfit_serve_t* sv, uint64_t ticket) {
   if (!sv) return serve_fail(SPOTFIT_E_NULL, "serve_poll: NULL");
   std::lock_guard<std::mutex> lk(sv->mu);
   if (ticket == 0 || ticket >= sv->next_ticket) return serve_fail(SPOTFIT_E_ARG, "serve_poll: unknown ticket");
-  if (ticket < sv->oldest_ticket) return SPOTFIT_OK;  // finished and released
+  if (ticket < sv->oldest_ticket)  // finished and released
+    return sv->failed_tickets.count(ticket) ? serve_fail(SPOTFIT_E_HIP, sv->error) : SPOTFIT_OK;
   const FrameRec& f = sv->rec(ticket);
   if (f.state == kDone) return SPOTFIT_OK;
   if (f.state == kFailed) return serve_fail(SPOTFIT_E_HIP, sv->error);

@@ -182,3 +182,28 @@ def test_graph_and_tracking_argument_errors():
     assert L.spotfit_graph_launch(None, None) == -1
     L.spotfit_graph_destroy(None)
     assert L.spotfit_serve_track(None, 4, None, 8) == -1
+
+
+def test_serve_frame_is_validated_before_the_c_call():
+    """Server.make_frame checks dtype, shapes and the pixel count the sizes name,
+    so the C submit never copies past a host buffer."""
+    import numpy as np
+    sizes = np.array([[9, 9, 0, 0], [13, 13, 0, 0]], np.uint8)
+    npx = 81 + 169
+    init = np.zeros((2, 4), np.float32)
+    f, _, outs = sf.Server.make_frame(np.zeros(npx, np.uint16), sizes, init)
+    assert f.n_spots == 2 and outs["params"].shape == (2, 6)
+    sf.Server.make_frame(np.zeros(npx, np.float32), sizes, None)
+    for bad in (np.zeros(npx, np.float64), np.zeros(npx, np.int16), np.zeros(npx, np.uint8)):
+        with pytest.raises(TypeError):
+            sf.Server.make_frame(bad, sizes, init)
+    with pytest.raises(ValueError):
+        sf.Server.make_frame(np.zeros(npx - 1, np.uint16), sizes, init)
+    with pytest.raises(TypeError):
+        sf.Server.make_frame(np.zeros(npx, np.uint16), sizes.astype(np.int32), init)
+    with pytest.raises(TypeError):
+        sf.Server.make_frame(np.zeros(npx, np.uint16), sizes[:, :3], init)
+    with pytest.raises(TypeError):
+        sf.Server.make_frame(np.zeros(npx, np.uint16), sizes, init[:1])
+    with pytest.raises(TypeError):
+        sf.Server.make_frame(np.zeros(npx, np.uint16), sizes, init.astype(np.float64))

@@ -105,6 +105,34 @@ def test_graph_mixed_schedule():
     g.close()
 
 
+def test_graph_mixed_schedule_survives_workspace_growth():
+    """The graph keeps its own mixed-schedule workspace: growing the context's
+    (a larger mixed call, an explicit reserve) between replays changes nothing."""
+    import torch
+
+    import paper_2106_02045_amd as sf
+    ctx = sf.Context(0)
+    b = spotgen.workload("mixed_7to32", n=2000)
+    big = spotgen.workload("mixed_7to32", n=30000, seed=77)
+    opts = sf.default_options(schedule=sf.SCHEDULE_MIXED)
+    d = dict(data=_up(b.data), sizes=_up(b.sizes), offsets=_up(b.offsets), init=_up(b.init))
+    g = ctx.graph(d["data"], d["sizes"], d["offsets"], d["init"], opts)
+    want = _direct(ctx, b, opts)
+    for step in range(3):
+        if step == 1:
+            _direct(ctx, big, opts)      # grows the context's workspace
+        if step == 2:
+            ctx.reserve(200000)          # and again
+        for t in g.out.values():
+            t.zero_()
+        _eager_noise()
+        g.launch()
+        torch.cuda.synchronize()
+        for k in ("params", "chi2", "iters", "status"):
+            np.testing.assert_array_equal(g.out[k].cpu().numpy(), want[k])
+    g.close()
+
+
 @pytest.mark.parametrize("kw", [dict(max_side=13), dict(max_side=13, plan_hint=1),
                                 dict(schedule=1), dict(max_side=13, precision=0)],
                          ids=["throughput", "latency", "mixed", "fp32"])

@@ -106,6 +106,38 @@ def test_serving_admission_by_memory(sf):
     np.testing.assert_array_equal(alone["params"], results[11]["params"])
 
 
+def test_serving_reports_a_failed_frame_after_its_release(sf, monkeypatch):
+    """A frame whose batch fails stays failed: wait() raises for it, also once its
+    ring space has been released and reused, and the other frames complete.  The
+    failure is forced on the host (the second batch is not enqueued at all)."""
+    monkeypatch.setenv("SPOTFIT_SERVE_FAIL_BATCH", "2")
+    ts, frames = spotgen.serve_frames(40, fps=1000.0, seed=12, threads=4)
+    opts = sf.default_options(max_side=21)
+    srv = sf.Server(0, opts, device_mem_budget=1 << 20, max_frames=4, n_streams=1)
+    tickets = []
+    for i, f in enumerate(frames[:3]):
+        r = srv.submit(f.data, f.sizes, f.init)
+        assert r is not None
+        tickets.append(r[0])
+        if i == 1:
+            with pytest.raises(sf.SpotfitError, match="injected failure"):
+                srv.wait(r[0])
+        else:
+            srv.wait(r[0])
+    # more frames than slots: the failed frame's slot and ring space are reused
+    import time
+    for f in frames[3:]:
+        while srv.submit(f.data, f.sizes, f.init) is None:
+            time.sleep(2e-4)
+    for t in range(tickets[-1] + 1, tickets[-1] + 1 + len(frames) - 3):
+        srv.wait(t)
+    assert srv.poll(tickets[1]) < 0
+    assert srv.poll(tickets[0]) == 0 and srv.poll(tickets[2]) == 0
+    st = srv.stats()
+    srv.close()
+    assert st["frames_failed"] == 1 and st["frames_done"] == len(frames) - 1
+
+
 def test_serving_with_device_start_values(sf):
     # frames without start values: the loop computes them on the device, inside
     # the fit's launch; the results equal a direct fit_raw of the same spots, bit
