@@ -11,6 +11,18 @@ diagonal entry: below pivot_band, rounding in the normal equations moves the
 step by more than the decisions can absorb).  Such spots are counted and
 reported, and must still satisfy the parameter tolerances when they end with
 the same status and are not ill-conditioned.
+
+Degenerate fits (with sigma_min given): an oracle fit that ends with a
+non-positive amplitude (no spot above the background) or with a width on the
+lower bound of limit() (a profile narrower than a pixel, whose position and
+amplitude trade off along the nearest pixel's value) has no unique minimum at
+the stopping resolution of the loop: both sides may stop anywhere along the flat
+direction, and a trajectory that wanders along such a direction for several
+iterations can end after a different number of them, or at a different point,
+on the other side's rounding.  Such spots (counted as n_degenerate) are excused
+from the status, iteration and parameter comparison and must instead end valid:
+a stop reason other than BAD_INPUT, finite parameters, widths not below the
+bound.  Callers bound how many there may be.
 """
 from __future__ import annotations
 
@@ -27,7 +39,7 @@ def _rel(a, b):
 
 
 def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None,
-            pivot_band: float = 0.0) -> dict:
+            pivot_band: float = 0.0, sigma_min=None) -> dict:
     """g: GPU outputs (params [n,6] f32, chi2, iters, status); r: oracle.fit_batch dict."""
     gp = np.asarray(g["params"], dtype=np.float64)
     rp = r["params"]
@@ -53,10 +65,18 @@ def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None,
     ill = r["min_pivot"] < pivot_band if "min_pivot" in r else np.zeros(n, bool)
     knife = knife | ill
     in_tol = (dxy < TOL_XY) & (relmax < TOL_REL) & (rchi < TOL_CHI)
+    deg = np.zeros(n, bool)
+    if sigma_min is not None:
+        deg = ~bad_in & ((rp[:, 4] <= 0.0) |
+                         (np.minimum(rp[:, 2], rp[:, 3]) <= sigma_min * (1.0 + 1e-9)))
+        valid = np.all(np.isfinite(gp), 1) & (g["status"] != 5) & \
+            (np.minimum(gp[:, 2], gp[:, 3]) >= sigma_min * (1.0 - 1e-6))
+        in_tol = np.where(deg, valid, in_tol)
     in_tol = np.where(bad_in, True, in_tol)
     # BAD_INPUT: status must match and outputs must be NaN on both sides
     nan_ok = np.all(np.isnan(gp[bad_in]))
     same = same_status & same_iters
+    knife = knife | deg
     strict = ~knife
     return dict(
         n=n,
@@ -68,11 +88,13 @@ def compare(g: dict, r: dict, chi_band: float, step_band: float, model=None,
         tol_fail_any=int((~in_tol).sum()),
         tol_fail_strict=int((~knife & ~in_tol).sum()),
         n_ill=int(ill.sum()),
+        n_degenerate=int(deg.sum()),
         max_dxy=float(np.nanmax(np.where(bad_in, 0, dxy))) if n else 0.0,
         max_rel=float(np.nanmax(np.where(bad_in, 0, relmax))) if n else 0.0,
         max_rchi=float(np.nanmax(np.where(bad_in, 0, rchi))) if n else 0.0,
         med_rchi=float(np.nanmedian(rchi[~bad_in])) if (~bad_in).any() else 0.0,
         bad_input_nan=bool(nan_ok),
+        strict_mask=strict,
         mismatch_idx=np.nonzero(~same)[0],
         fail_idx=np.nonzero((strict & ~same) | (~knife & ~in_tol))[0],
     )
@@ -94,6 +116,7 @@ def describe(g: dict, r: dict, idx, limit: int = 8) -> str:
 
 def summary(name: str, c: dict) -> str:
     return (f"{name}: n={c['n']} knife={c['n_knife']} (ill-conditioned {c['n_ill']}) "
+            f"degenerate={c.get('n_degenerate', 0)} "
             f"status_mis={c['status_mismatch']} "
             f"iters_mis={c['iters_mismatch']} strict_mis={c['strict_mismatch']} "
             f"tol_fail(same)={c['tol_fail_same']} tol_fail(any)={c['tol_fail_any']} "
