@@ -71,7 +71,7 @@ typedef enum {
   SPOTFIT_MAX_ITER = 0,      /* iteration budget used up after an accepted step          */
   SPOTFIT_MAX_ERROR = 1,     /* chi^2 below max_error_per_px * w*h                       */
   SPOTFIT_MIN_DELTA = 2,     /* chi*(1 - min_delta) < Chi: too small an improvement      */
-  SPOTFIT_MIN_STEP = 3,      /* every |delta_j| < min_step_rel * |p_j|                   */
+  SPOTFIT_MIN_STEP = 3,      /* every |delta_j| < min_step_rel * |p_j - o_j| (o: below)  */
   SPOTFIT_NOT_CONVERGED = 4, /* NaN error, or no decrease after the damping retries;
                                 the parameters before the failed step are returned    */
   SPOTFIT_BAD_INPUT = 5      /* spot-level input error, see above                       */
@@ -137,7 +137,10 @@ typedef struct {
   int32_t precision;        /* spotfit_precision_t                                          */
   double max_error_per_px;  /* MaxError iff chi^2 < this * w*h (paper "A/3" -> 1/3)        */
   double min_delta;         /* MinDelta iff chi*(1 - min_delta) < Chi (paper: 1e-6)         */
-  double min_step_rel;      /* MinStep iff all |delta_j| < this * |p_j| (paper: 1e-4)       */
+  double min_step_rel;      /* MinStep iff all |delta_j| < this * |p_j - o_j| (paper: 1e-4),
+                               o_j = the ROI centre ((w-1)/2, (h-1)/2) for x and y, 0 for
+                               the widths (Number of iterations section: < 1 % of the
+                               Fig. 8 fits stop on this test)                              */
   double tie_tau;           /* chi^2 changes within +-tie_tau*chi count as ties: neither
                                "improved" nor "worse"; 0 = the paper's exact comparisons  */
   double sigma_min;         /* parameter box of limit(): sigma >= sigma_min (0.3)          */

@@ -48,7 +48,7 @@ typedef struct {
   int32_t max_iter;          /* iteration budget (paper: 20)                          */
   double  max_error_per_px;  /* MaxError iff chi^2 < max_error_per_px * N  ("A/3")    */
   double  min_delta;         /* MinDelta iff chi*(1-min_delta) < Chi   (paper: 1e-6)  */
-  double  min_step_rel;      /* MinStep iff all |delta_j| < min_step_rel*|p_j| (1e-4) */
+  double  min_step_rel;      /* MinStep iff all |delta_j| < min_step_rel*|p_j - o_j|, o = ROI centre for x, y (1e-4) */
   int32_t lambda0_exp10;     /* initial damping 10^k0 (paper: 0.01 -> -2)             */
   int32_t lambda_max_exp10;  /* retries while k < this (paper: 10^4 -> 4)             */
   double  tie_tau;           /* relative tie band for chi^2 comparisons (0 = verbatim) */

@@ -342,10 +342,15 @@ __device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * 
       } else {
         const double Chi = S.chi, chi = S.chi_best;
         if (mode == kTrialFirst && Chi < chi * (1.0 - tau)) --k;  // improved: less damping
+        // MinStep: every step below min_step_rel of its parameter, the centre
+        // measured from the centre of the ROI
         bool small = true;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          small = small && ((sym && q == 3) || fabs(S.delta[q]) < o.min_step_rel * fabs(S.best[q]));
+        for (int q = 0; q < 4; ++q) {
+          const double org = q == 0 ? 0.5 * double(w - 1) : q == 1 ? 0.5 * double(h - 1) : 0.0;
+          small = small &&
+                  ((sym && q == 3) || fabs(S.delta[q]) < o.min_step_rel * fabs(S.best[q] - org));
+        }
         const bool worse = chi * (1.0 + tau) < Chi;
         if (!small && worse && k < o.lambda_max_exp10) {
           ++k;  // more damping, retry from best

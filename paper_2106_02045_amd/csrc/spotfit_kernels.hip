@@ -318,11 +318,13 @@ __device__ __forceinline__ void limit_p(S (&p)[Np<MODEL>::v], int w, int h, cons
 }
 
 template <int NP, typename S>
-__device__ __forceinline__ bool all_small(const S (&d)[NP], const S (&best)[NP], S rel) {
+// MinStep: every |d_j| below rel times its parameter, the centre coordinates
+// measured from the centre (cx, cy) of the ROI.
+__device__ __forceinline__ bool all_small(const S (&d)[NP], const S (&best)[NP], S rel, S cx, S cy) {
   bool all = true;
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
-    const S lim = rel * fabs_s(best[j]);
+    const S lim = rel * fabs_s(best[j] - (j == 0 ? cx : j == 1 ? cy : S(0)));
     all = all && (fabs_s(d[j]) < lim);
   }
   return all;
@@ -349,6 +351,7 @@ __device__ SpotOut lm_fit(const Pixels<PPL>& px, int N, S G, const float* init4,
   const S tau = S(o.tie_tau);
   const S min_delta = S(o.min_delta);
   const S min_step = S(o.min_step_rel);
+  const S cx = S(0.5) * S(w - 1), cy = S(0.5) * S(h - 1);  // centre of the ROI
   int k = o.lambda0_exp10;
   int it = 0, status = SPOTFIT_MAX_ITER, n_grad = 0, n_trial = 0;
 
@@ -376,7 +379,7 @@ __device__ SpotOut lm_fit(const Pixels<PPL>& px, int N, S G, const float* init4,
     ++n_trial;
     if (cur.chi < chi * (S(1) - tau)) --k;  // improved: less damping
 
-    while (!all_small<NP, S>(delta, best, min_step) && (chi * (S(1) + tau) < cur.chi) &&
+    while (!all_small<NP, S>(delta, best, min_step, cx, cy) && (chi * (S(1) + tau) < cur.chi) &&
            k < o.lambda_max_exp10) {
       ++k;  // worse: more damping, retry from best
       damped_solve<NP, S>(A, bv, pow10_s<S>(k), delta);
@@ -395,7 +398,7 @@ __device__ SpotOut lm_fit(const Pixels<PPL>& px, int N, S G, const float* init4,
     }
     if (cur.chi < T) { status = SPOTFIT_MAX_ERROR; break; }
     if (chi * (S(1) - min_delta) < cur.chi) { status = SPOTFIT_MIN_DELTA; break; }
-    if (all_small<NP, S>(delta, best, min_step)) { status = SPOTFIT_MIN_STEP; break; }
+    if (all_small<NP, S>(delta, best, min_step, cx, cy)) { status = SPOTFIT_MIN_STEP; break; }
   }
 
   out.p[0] = float(p[0]);

@@ -723,7 +723,10 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         pc[1] = clampn(b1 + d[1], -0.5, double(h) - 0.5);
         pc[2] = p2;
         pc[3] = sym ? p2 : clampn(b3 + d[3], o.sigma_min, smax);
-        small = fabs(d[0]) < o.min_step_rel * fabs(b0) && fabs(d[1]) < o.min_step_rel * fabs(b1) &&
+        // MinStep: every step below min_step_rel of its parameter, the centre
+        // measured from the centre of the ROI
+        small = fabs(d[0]) < o.min_step_rel * fabs(b0 - 0.5 * double(w - 1)) &&
+                fabs(d[1]) < o.min_step_rel * fabs(b1 - 0.5 * double(h - 1)) &&
                 fabs(d[2]) < o.min_step_rel * fabs(b2) &&
                 (sym || fabs(d[3]) < o.min_step_rel * fabs(b3));
       }

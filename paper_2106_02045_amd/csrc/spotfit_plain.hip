@@ -155,7 +155,10 @@ __device__ void fit(const Pix& px, int N, int w, int h, float G, const float* in
   };
   auto small_all = [&]() {
     bool s = true;
-    for (int j = 0; j < NP; ++j) s = s && fabsf(delta[j]) < float(o.min_step_rel) * fabsf(best[j]);
+    // the centre coordinates measured from the centre of the ROI
+    const float org[2] = {0.5f * float(w - 1), 0.5f * float(h - 1)};
+    for (int j = 0; j < NP; ++j)
+      s = s && fabsf(delta[j]) < float(o.min_step_rel) * fabsf(best[j] - (j < 2 ? org[j] : 0.f));
     return s;
   };
   float chi_out = 0.f;  // error at the point that is returned

@@ -223,4 +223,4 @@ def test_fig8_on_device():
     print("iterations", np.round(hist[:10], 3), "stops", np.round(frac, 4))
     assert frac[sf.MIN_DELTA] > 0.5
     assert frac[sf.MAX_ITER] < 0.005
-    assert frac[sf.MIN_STEP] < 0.1
+    assert frac[sf.MIN_STEP] < gold["min_step_fraction_below"]

@@ -330,8 +330,9 @@ def test_fig8_iteration_and_stop_statistics():
     st = np.bincount(r["status"], minlength=6) / b.n
     assert st[oracle.MIN_DELTA] > 0.5
     assert st[oracle.MAX_ITER] < 0.005
-    # double precision keeps MinStep rare, though above the paper's single-precision < 1 %
-    assert st[oracle.MIN_STEP] < 0.1
+    # fewer than 1 % reach the minimal parameter change criterion (with the centre
+    # measured from the ROI centre; from the corner pixel about 5 % would)
+    assert st[oracle.MIN_STEP] < gold["min_step_fraction_below"]
 
 
 # ---------------------------------------------------------------------------
@@ -417,6 +418,8 @@ def _replay(g, w, h, model, init, kw, res, events):
         return np.linalg.solve(A + 10.0 ** k * np.diag(np.diag(A)), b)
 
     p = np.asarray(init, dtype=np.float32).astype(np.float64)[:n]
+    # MinStep measures the centre from the centre of the ROI
+    org = np.array([(w - 1) / 2.0, (h - 1) / 2.0, 0.0, 0.0])[:n]
     k, it, status, branch = o["lambda0_exp10"], 0, oracle.MAX_ITER, "max_iter"
     retried = False
     while it < o["max_iter"]:
@@ -431,13 +434,13 @@ def _replay(g, w, h, model, init, kw, res, events):
         p, Chi = take(oracle.EV_TRIAL, it, k, limit(best + d), d)
         if Chi < chi:
             k -= 1
-        small = bool(np.all(np.abs(d) < o["min_step_rel"] * np.abs(best)))
+        small = bool(np.all(np.abs(d) < o["min_step_rel"] * np.abs(best - org)))
         while not small and Chi > chi and k < o["lambda_max_exp10"]:
             k += 1
             retried = True
             d = solve(A, b, k)
             p, Chi = take(oracle.EV_RETRY, it, k, limit(best + d), d)
-            small = bool(np.all(np.abs(d) < o["min_step_rel"] * np.abs(best)))
+            small = bool(np.all(np.abs(d) < o["min_step_rel"] * np.abs(best - org)))
         if Chi > chi:
             p = best
             status = oracle.NOT_CONVERGED
