@@ -185,6 +185,31 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
                       float* chi2_out, int32_t* iters_out, int32_t* status_out,
                       int32_t* evals_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call, arguments and results as spotfit_fit_spots (bit for bit, with the same
+ * context and options), but the fit's scratch memory -- the spot counter of
+ * the uniform schedule, the counters and size-class lists of the mixed
+ * schedule -- is a fixed array of the library in device memory instead of the
+ * context's workspace.  The array is 4 * (72 + 3 * SPOTFIT_NOALLOC_MAX_SPOTS)
+ * bytes (about 12.6 MB) on every GPU the library runs on, held until the
+ * process ends; its address on a device is looked up when the first context
+ * on that device is created.  The call allocates nothing and never grows the
+ * context's workspace.  Mixed schedule: at most SPOTFIT_NOALLOC_MAX_SPOTS
+ * spots per call (SPOTFIT_E_ARG beyond, checked before any HIP call); the
+ * uniform schedule and the single-precision kernels take any n_spots.  Each
+ * call clears the counters it uses with a kernel on `stream` before the fit.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (on other streams, from other contexts or host threads) race on it
+ * and give wrong results; the caller orders them (calls on one stream are
+ * ordered by the stream).  Returns SPOTFIT_OK or a negative spotfit_error_t. */
+#define SPOTFIT_NOALLOC_MAX_SPOTS (1 << 20)
+int spotfit_fit_spots_noalloc(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                              const spotfit_shape_t* sizes, const int64_t* offsets,
+                              const float* init, int64_t n_spots, const spotfit_options_t* opt,
+                              float* params_out, float* chi2_out, int32_t* iters_out,
+                              int32_t* status_out, int32_t* evals_out, void* stream);
+
 /* Start values on the device, so that raw spots go in and fits come out
  * without a host round trip (the paper takes start values as given and leaves
  * them out of its timings, Results section).  The estimate: background b0 =

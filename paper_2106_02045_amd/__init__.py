@@ -30,8 +30,9 @@ EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_
             "spotfit_serve_last_error", "spotfit_get_stats", "spotfit_autotune",
             "spotfit_moment_init", "spotfit_peak_init", "spotfit_serve_track",
             "spotfit_graph_create", "spotfit_graph_launch", "spotfit_graph_destroy",
-            "spotfit_fit_raw"]
+            "spotfit_fit_raw", "spotfit_fit_spots_noalloc"]
 E_AGAIN = -6
+NOALLOC_MAX_SPOTS = 1 << 20
 
 
 class SpotfitError(RuntimeError):
@@ -167,6 +168,8 @@ def lib():
         L.spotfit_fit_spots.argtypes = [vp, vp, i32, vp, vp, vp, i64, ctypes.POINTER(Options),
                                         vp, vp, vp, vp, vp, vp]
         L.spotfit_fit_spots.restype = ctypes.c_int
+        L.spotfit_fit_spots_noalloc.argtypes = L.spotfit_fit_spots.argtypes
+        L.spotfit_fit_spots_noalloc.restype = ctypes.c_int
         L.spotfit_fit_raw.argtypes = [vp, vp, i32, vp, vp, i64, ctypes.POINTER(Options), vp,
                                       vp, vp, vp, vp, vp, vp]
         L.spotfit_fit_raw.restype = ctypes.c_int
@@ -335,6 +338,24 @@ class Context:
                                 out["evals"].data_ptr() if "evals" in out else 0,
                                 st.cuda_stream)
         _check(rc, "spotfit_fit_spots")
+        return out
+
+    def fit_spots_noalloc(self, data, sizes, offsets, init, opts: Optional[Options] = None,
+                          out=None, want_evals: bool = False, stream=None):
+        """spotfit_fit_spots_noalloc: fit_spots whose counters and size-class lists are
+        the library's fixed device array instead of the context's workspace.  `out`
+        should be supplied by callers that must not allocate (otherwise torch
+        allocates the outputs here)."""
+        import torch
+        n, dt, out = self._marshal(data, sizes, offsets, init, out, want_evals)
+        st = stream if stream is not None else torch.cuda.current_stream(data.device)
+        rc = lib().spotfit_fit_spots_noalloc(
+            self._h, data.data_ptr(), dt, sizes.data_ptr(), offsets.data_ptr(),
+            init.data_ptr(), n, ctypes.byref(opts) if opts is not None else None,
+            out["params"].data_ptr(), out["chi2"].data_ptr(), out["iters"].data_ptr(),
+            out["status"].data_ptr(), (out["evals"].data_ptr() if "evals" in out else 0) or None,
+            st.cuda_stream or None)
+        _check(rc, "spotfit_fit_spots_noalloc")
         return out
 
     def fit_raw(self, data, sizes, offsets, opts: Optional[Options] = None, out=None,

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -30,7 +31,18 @@ struct spotfit_ctx {
   int64_t ws_cap;
   unsigned long long* stats;  // device histogram buffer of spotfit_get_stats
   int32_t* queue;             // spot counter of the narrow kernel's uniform launches
+  int32_t* scratch;           // device address of this device's copy of `scratch` (below)
 };
+
+// Scratch memory of spotfit_fit_spots_noalloc: word 0 the uniform schedule's
+// spot counter; from word 64 (256 bytes in) the mixed schedule's 8 counters and
+// its 3 size-class lists of SPOTFIT_NOALLOC_MAX_SPOTS spot indices.  Every GPU
+// holds its own copy at its own address.  In host code this name only stands
+// for the array: kernels get the address that hipGetSymbolAddress returns for
+// the current device (kept per device in g_scratch_addr and in each context).
+constexpr int64_t kScratchMixedAt = 64;
+constexpr int64_t kScratchWords = kScratchMixedAt + 8 + 3 * (int64_t)SPOTFIT_NOALLOC_MAX_SPOTS;
+static __device__ __align__(256) int32_t scratch[kScratchWords];
 
 namespace {
 
@@ -48,6 +60,28 @@ int fail_hip(hipError_t e, const char* where) {
 
 int fail(int code, const std::string& what) { return fail(code, what.c_str()); }
 int fail_hip(hipError_t e, const std::string& where) { return fail_hip(e, where.c_str()); }
+
+// Device address of `scratch` on each device, looked up once per device (with
+// that device current) by the first context created there.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_addr[kMaxDevices] = {};
+
+// Address of `scratch` on `device`, which must be current.
+hipError_t scratch_address(int device, int32_t** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = static_cast<int32_t*>(ptr);
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 int ppl_index(int ppl) {
   switch (ppl) {
@@ -208,6 +242,12 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
   c->ws_cap = 0;
   c->stats = nullptr;
   c->queue = nullptr;
+  c->scratch = nullptr;
+  e = scratch_address(device, &c->scratch);
+  if (e != hipSuccess) {
+    delete c;
+    return fail_hip(e, "hipGetSymbolAddress (no-allocation scratch)");
+  }
   e = hipMalloc((void**)&c->stats, sizeof(unsigned long long) * kStatsLen);
   if (e == hipSuccess) e = hipMalloc((void**)&c->queue, 256);
   if (e != hipSuccess) {
@@ -324,7 +364,8 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
                const int64_t* offsets, const float* init, int64_t n, const spotfit_options_t& o,
                float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
                int32_t* evals_out, void* stream, float* init_out = nullptr,
-               const sf::MixedWs* classified = nullptr, const sf::MixedWs* own_ws = nullptr) {
+               const sf::MixedWs* classified = nullptr, const sf::MixedWs* own_ws = nullptr,
+               int32_t* own_queue = nullptr) {
   sf::KArgs ka;
   std::memset(&ka, 0, sizeof ka);
   ka.data = data;
@@ -337,7 +378,7 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   ka.iters_out = iters_out;
   ka.status_out = status_out;
   ka.evals_out = evals_out;
-  ka.queue = ctx->queue;
+  ka.queue = own_queue ? own_queue : ctx->queue;
   ka.n = n;
   ka.dtype = dtype;
   ka.opt.max_iter = o.max_iter;
@@ -472,6 +513,28 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
   if (rc != SPOTFIT_OK || n == 0) return rc;
   return launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
                     status_out, evals_out, stream);
+}
+
+int spotfit_fit_spots_noalloc(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
+                              const spotfit_shape_t* sizes, const int64_t* offsets,
+                              const float* init, int64_t n, const spotfit_options_t* opt,
+                              float* params_out, float* chi2_out, int32_t* iters_out,
+                              int32_t* status_out, int32_t* evals_out, void* stream) {
+  spotfit_options_t o;
+  int rc = check_call(ctx, data, dtype, sizes, offsets, init, n, opt, params_out, chi2_out,
+                      iters_out, status_out, &o, "fit_spots_noalloc");
+  if (rc != SPOTFIT_OK || n == 0) return rc;
+  if (o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED &&
+      n > (int64_t)SPOTFIT_NOALLOC_MAX_SPOTS)
+    return fail(SPOTFIT_E_ARG, "fit_spots_noalloc: a mixed-schedule call takes at most "
+                               "SPOTFIT_NOALLOC_MAX_SPOTS (1048576) spots");
+  if (!ctx->scratch) return fail(SPOTFIT_E_DEVICE, "fit_spots_noalloc: no scratch address");
+  // the counters and lists live in this device's copy of `scratch`; the
+  // kernels that use them clear the counters first (no memset, no allocation)
+  const sf::MixedWs ws{ctx->scratch + kScratchMixedAt, ctx->scratch + kScratchMixedAt + 8,
+                       (int64_t)SPOTFIT_NOALLOC_MAX_SPOTS};
+  return launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
+                    status_out, evals_out, stream, nullptr, nullptr, &ws, ctx->scratch);
 }
 
 int spotfit_fit_raw(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
