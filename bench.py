@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 # instructions, which the library's kernels are compiled without.)
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBPS = 8000.0
+CLOCK_HZ = 2.4e9  # peak engine clock
 
 # Algorithmic work per spot of N pixels with n_g derivative and n_t trial
 # evaluations: N * (C_g n_g + C_t n_t - 11 (n_g - 1)) flop, exp count N (n_t + 1).
@@ -63,6 +64,39 @@ def measured_traffic(workload: str, precision: str, schedule: str):
     return t["hbm_bytes_per_launch"]
 
 
+def measured_counters(workload: str, precision: str, schedule: str):
+    """Per-launch hardware counters of the fit kernel from the committed summary
+    (rocprofv3 --pmc over one launch), or None when no summary exists for this
+    configuration or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}_{precision}_{schedule}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    t["_path"] = path
+    return t
+
+
+def host_cpu() -> dict:
+    """Logical CPUs of the host, those this process may run on, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return {"nproc": os.cpu_count(), "allowed": allowed, "model": model}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,7 +104,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale_15x15")
     ap.add_argument("--n", type=int, default=None, help="spots (default: the workload's size)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32", "plain"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp32", "plain", "comp"])
     ap.add_argument("--tie-tau", type=float, default=0.0)
     ap.add_argument("--schedule", default="uniform", choices=["uniform", "mixed", "per-size"],
                     help="uniform: one lane-group width for the batch; mixed: one persistent "
@@ -86,6 +120,11 @@ def parse():
                          "calibration dispatch for hardware traffic counters")
     ap.add_argument("--parity-sample", type=int, default=2000,
                     help="spots compared with the CPU oracle after the timed run (0: none)")
+    ap.add_argument("--serve-frames", type=int, default=10000,
+                    help="after the timed fit steps, replay this many camera frames of the "
+                         "serving workload at --serve-fps (Poisson arrivals) through the "
+                         "serving loop and report their latency (0: skip)")
+    ap.add_argument("--serve-fps", type=float, default=1000.0)
     return ap.parse_args()
 
 
@@ -114,7 +153,7 @@ def main():
     data, sizes, offs, init = up(batch.data), up(batch.sizes), up(batch.offsets), up(batch.init)
     ctx = sf.Context(0)
     prec = {"fp64": sf.PREC_FP64, "mixed": sf.PREC_MIXED, "fp32": sf.PREC_FP32,
-            "plain": sf.PREC_FP32_PLAIN}[a.precision]
+            "plain": sf.PREC_FP32_PLAIN, "comp": sf.PREC_COMP}[a.precision]
     max_side = int(max(batch.sizes[:, 0].max(), batch.sizes[:, 1].max()))
     opts = sf.default_options(precision=prec, max_pixels=max(9, max_px), max_side=max(3, max_side),
                               tie_tau=a.tie_tau,
@@ -191,19 +230,55 @@ def main():
     achieved_tflops = flops / k_avg_s / 1e12
     hbm_gbps = alg_bytes / k_avg_s / 1e9
 
+    # serving: frames with Poisson arrivals through the serving loop (outside the
+    # timed region; its own clock is per frame, arrival -> results on the host)
+    serve = None
+    if a.serve_frames > 0:
+        from paper_2106_02045_amd import serve_bench
+        sv = serve_bench.run(["--frames", str(a.serve_frames), "--fps", str(a.serve_fps),
+                              "--streams", "2", "--check", "20"])
+        serve = {"workload": "serve_fiducials", "frames": sv["frames"],
+                 "fps_offered": sv["fps_offered"], "fps_achieved": sv["fps_achieved"],
+                 "p50_us": sv["latency_p50_us"], "p99_us": sv["latency_p99_us"],
+                 "max_us": sv["latency_max_us"], "fits_per_s": sv["fits_per_s"],
+                 "frames_per_launch": sv["mean_frames_per_batch"], "plan": sv["plan"],
+                 "warmup_frames": sv["warmup_frames"],
+                 "alone_vs_mix_differing": sv["alone_vs_mix"]["frames_differing"]}
+
+    # issue utilisation from the hardware counters of one launch of this kernel
+    # build (committed summary, stamped with the sources' hash): VALU wave
+    # instructions x 4 cycles over the SIMD cycles of the measured launch time
+    valu = None
+    cnt = measured_counters(a.workload, a.precision, a.schedule)
+    if cnt is not None:
+        simd_cycles = 256 * 4 * CLOCK_HZ * k_avg_s
+        f64 = cnt["SQ_INSTS_VALU_FMA_F64"] * 2 + cnt["SQ_INSTS_VALU_MUL_F64"] + \
+            cnt["SQ_INSTS_VALU_ADD_F64"]
+        valu = {"issue_frac": cnt["SQ_INSTS_VALU"] * 4 / simd_cycles,
+                "fp64_flop_frac": f64 * 64 / k_avg_s / (PEAK_ALU_TFLOPS * 1e12),
+                "valu_insts_per_launch": cnt["SQ_INSTS_VALU"],
+                "fp64_flops_per_launch": f64 * 64,
+                "busy_frac_counters": cnt.get("valu_busy_frac"),
+                "source": os.path.join("profiles", os.path.basename(cnt["_path"]))
+                if "_path" in cnt else None}
+
     cpu = None
     if not a.no_cpu_baseline:
         import oracle
         m = min(a.cpu_sample, n)
         sub = spotgen.workload(a.workload, n=m)
-        threads = a.cpu_threads or min(os.cpu_count() or 1, 16)
+        hc = host_cpu()
+        # at most 16 threads: the share of the host's cores that one GPU's jobs may use
+        threads = a.cpu_threads or min(hc["allowed"] or hc["nproc"] or 1, 16)
+        lib, flags = oracle.native_lib()
         oo = oracle.default_opts(tie_tau=a.tie_tau)
         c0 = time.perf_counter()
-        oracle.fit_batch(sub, oo, threads=threads)
+        oracle.fit_batch(sub, oo, threads=threads, library=lib)
         cs = time.perf_counter() - c0
         cpu = {"value": m / cs, "unit": "fits/s", "cores": threads, "kind": "oracle",
                "sample": f"first {m} spots of {a.workload} (same generator and seed), "
-                         f"{cs:.2f} s wall on {threads} threads"}
+                         f"{cs:.2f} s wall on {threads} threads",
+               "host": hc, "build": flags}
 
     parity = None
     if a.parity_sample > 0:
@@ -237,7 +312,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {sf.PREC_FP64: "f64", sf.PREC_MIXED: "f32+f64", sf.PREC_FP32: "f32",
-                  sf.PREC_FP32_PLAIN: "f32"}[prec],
+                  sf.PREC_FP32_PLAIN: "f32", sf.PREC_COMP: "f32 compensated+f64"}[prec],
         "data": "synthetic",
         "config": {"workload": a.workload, "spots": n, "roi": f"{batch.sizes[0,0]}x{batch.sizes[0,1]}"
                    if len(np.unique(npix)) == 1 else "mixed", "pixel_dtype": "u16",
@@ -253,6 +328,8 @@ def main():
         "evals_per_spot": {"grad": float(ng.mean()), "trial": float(nt.mean())},
         "status_hist": np.bincount(status, minlength=6).tolist(),
         "iters_mean": float(iters.mean()),
+        "valu": valu,
+        "serve": serve,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
         "gen_s": gen_s,

@@ -87,9 +87,14 @@ typedef enum {
   SPOTFIT_PREC_FP64 = 2,  /* default: separable kernel, the profile factors into
                              exp(column) * exp(row); every evaluation in double
                              precision, so chi^2 comparisons see ~1e-15 relative error */
-  SPOTFIT_PREC_FP32_PLAIN = 3 /* the paper's own mapping as a baseline: one thread per
+  SPOTFIT_PREC_FP32_PLAIN = 3, /* the paper's own mapping as a baseline: one thread per
                              pixel, one workgroup per spot, one sum per quantity,
                              single precision everywhere                               */
+  SPOTFIT_PREC_COMP = 4   /* per-pixel profile kernel as MIXED, but every per-lane sum of
+                             an evaluation is compensated: the rounding error of each
+                             product (by fma) and of each addition (TwoSum) is carried
+                             in a second float, and the lane totals are combined in
+                             double; FP32 profile, FP64 determinant and LM solve      */
 } spotfit_precision_t;
 
 /* How the separable kernel maps a batch onto lane groups. */
@@ -458,6 +463,14 @@ const char* spotfit_last_error(void);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int spotfit_version(void);
+
+/* The exponential the double-precision kernels evaluate the profile factors of
+ * Eq. 10 with (arguments x <= 0: Cody-Waite reduction by ln 2, Taylor series of
+ * degree 13, scaling by 2^n), applied elementwise: y[i] = e^x[i] for the n
+ * device doubles x, written to the device array y, on `stream`.  For accuracy
+ * tests against a reference exponential.  x > 0 is outside its range.  Returns
+ * SPOTFIT_OK, SPOTFIT_E_NULL, SPOTFIT_E_ARG (n < 0) or SPOTFIT_E_HIP. */
+int spotfit_exp_neg(const double* x, double* y, int64_t n, void* stream);
 
 #ifdef __cplusplus
 }

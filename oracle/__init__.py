@@ -69,14 +69,17 @@ class Event(ctypes.Structure):
 EV_GRAD, EV_TRIAL, EV_RETRY = range(3)
 
 
+# the build the tests load (and that travels with the tree): baseline x86-64
+PORTABLE_FLAGS = ["-O3", "-ffp-contract=off", "-fno-fast-math"]
+
+
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc: baseline x86-64, no fast-math, no FMA contraction."""
     if force or not os.path.exists(LIB_PATH) or \
             os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
         tmp = LIB_PATH + ".tmp"
-        subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=gnu99", "-ffp-contract=off",
-                        "-fno-fast-math", "-Wall", "-o", tmp, SRC_PATH, "-lm", "-lpthread"],
-                       check=True)
+        subprocess.run(["gcc", *PORTABLE_FLAGS, "-fPIC", "-shared", "-std=gnu99", "-Wall", "-o",
+                        tmp, SRC_PATH, "-lm", "-lpthread"], check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -209,8 +212,34 @@ def fit_spot_traced(g, w: int, h: int, model: int, init4, opts: Optional[Opts] =
     return res, events
 
 
-def fit_batch(batch, opts: Optional[Opts] = None, threads: int = 1) -> dict:
-    """Fit every spot of a spotgen.SpotBatch; returns a dict of numpy arrays."""
+NATIVE_FLAGS = ["-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def native_lib(dest_dir: Optional[str] = None):
+    """The oracle compiled for this host's CPU (gcc -O3 -march=native, still no
+    fast-math and no FMA contraction, so every result is the same), for timing
+    it as a CPU baseline; built into a temporary directory on first use.
+    Returns (library, flags); the portable build if gcc fails."""
+    global _native
+    if _native is None:
+        import tempfile
+        d = dest_dir or tempfile.mkdtemp(prefix="oracle_native_")
+        path = os.path.join(d, "liboracle_native.so")
+        try:
+            subprocess.run(["gcc", *NATIVE_FLAGS, "-fPIC", "-shared", "-std=gnu99", "-o", path,
+                            SRC_PATH, "-lm", "-lpthread"], check=True, capture_output=True)
+            _native = (bind(ctypes.CDLL(path)), " ".join(["gcc", *NATIVE_FLAGS]))
+        except (OSError, subprocess.CalledProcessError):
+            _native = (lib(), " ".join(["gcc", *PORTABLE_FLAGS]))
+    return _native
+
+
+_native = None
+
+
+def fit_batch(batch, opts: Optional[Opts] = None, threads: int = 1, library=None) -> dict:
+    """Fit every spot of a spotgen.SpotBatch; returns a dict of numpy arrays.
+    library: a loaded build of the oracle (default: the portable one)."""
     n = batch.n
     o = opts if opts is not None else default_opts()
     data = np.ascontiguousarray(batch.data)
@@ -229,7 +258,8 @@ def fit_batch(batch, opts: Optional[Opts] = None, threads: int = 1) -> dict:
                min_pivot=np.zeros(n))
     if n == 0:
         return out
-    rc = lib().orc_fit_batch(data.ctypes.data, dtype, sizes.ctypes.data, offs.ctypes.data,
+    L = library if library is not None else lib()
+    rc = L.orc_fit_batch(data.ctypes.data, dtype, sizes.ctypes.data, offs.ctypes.data,
                              init.ctypes.data, n, ctypes.byref(o),
                              *(out[k].ctypes.data for k in ("params", "chi2", "iters", "status",
                                                             "n_grad", "n_trial", "margin_chi",

@@ -18,7 +18,7 @@ U16, F32 = 0, 1
 SYM, ELL = 0, 1
 MAX_ITER, MAX_ERROR, MIN_DELTA, MIN_STEP, NOT_CONVERGED, BAD_INPUT = range(6)
 STATUS_NAMES = ["MAX_ITER", "MAX_ERROR", "MIN_DELTA", "MIN_STEP", "NOT_CONVERGED", "BAD_INPUT"]
-PREC_FP32, PREC_MIXED, PREC_FP64, PREC_FP32_PLAIN = 0, 1, 2, 3
+PREC_FP32, PREC_MIXED, PREC_FP64, PREC_FP32_PLAIN, PREC_COMP = 0, 1, 2, 3, 4
 SCHEDULE_UNIFORM, SCHEDULE_MIXED = 0, 1
 PLAN_THROUGHPUT, PLAN_LATENCY = 0, 1
 
@@ -30,7 +30,7 @@ EXPORTED = ["spotfit_default_options", "spotfit_validate_options", "spotfit_ctx_
             "spotfit_serve_last_error", "spotfit_get_stats", "spotfit_autotune",
             "spotfit_moment_init", "spotfit_peak_init", "spotfit_serve_track",
             "spotfit_graph_create", "spotfit_graph_launch", "spotfit_graph_destroy",
-            "spotfit_fit_raw", "spotfit_fit_spots_noalloc"]
+            "spotfit_fit_raw", "spotfit_fit_spots_noalloc", "spotfit_exp_neg"]
 E_AGAIN = -6
 NOALLOC_MAX_SPOTS = 1 << 20
 
@@ -170,6 +170,8 @@ def lib():
         L.spotfit_fit_spots.restype = ctypes.c_int
         L.spotfit_fit_spots_noalloc.argtypes = L.spotfit_fit_spots.argtypes
         L.spotfit_fit_spots_noalloc.restype = ctypes.c_int
+        L.spotfit_exp_neg.argtypes = [vp, vp, i64, vp]
+        L.spotfit_exp_neg.restype = ctypes.c_int
         L.spotfit_fit_raw.argtypes = [vp, vp, i32, vp, vp, i64, ctypes.POINTER(Options), vp,
                                       vp, vp, vp, vp, vp, vp]
         L.spotfit_fit_raw.restype = ctypes.c_int
@@ -524,6 +526,19 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def exp_neg(x, stream=None):
+    """e^x (x <= 0) by the fit kernels' own exponential (spotfit_exp_neg), for a
+    float64 torch CUDA tensor; returns a new tensor."""
+    import torch
+    if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a contiguous float64 CUDA tensor")
+    y = torch.empty_like(x)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    _check(lib().spotfit_exp_neg(x.data_ptr(), y.data_ptr(), x.numel(), st.cuda_stream or None),
+           "spotfit_exp_neg")
+    return y
 
 
 def version() -> int:

@@ -14,12 +14,14 @@
 
 #include "spotfit.h"
 #include "spotfit_internal.h"
+#include "spotfit_lm.h"
 
 struct spotfit_ctx {
   int device;
   int n_cu;
-  // resident 64-lane workgroups per CU, per (ppl class, precision)
-  int occupancy[5][2];
+  // resident 64-lane workgroups per CU, per (ppl class, per-pixel precision:
+  // FP32, MIXED, COMP)
+  int occupancy[5][3];
   // separable kernel: plan used for each size class (max side <= 8, <= 16, <= 32)
   // and resident 64-lane workgroups per CU of every plan
   int plan_for_class[3];
@@ -129,6 +131,13 @@ __global__ __launch_bounds__(256) void stats_kernel(const int32_t* status, const
   if (blockIdx.x == 0 && threadIdx.x == 0) buf[0] = (unsigned long long)n;
 }
 
+// y = e^x with the fit kernels' own exponential (grid-stride over n values)
+__global__ __launch_bounds__(256) void exp_neg_kernel(const double* x, double* y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = sf::lm::exp_neg(x[i]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -159,7 +168,8 @@ int spotfit_validate_options(const spotfit_options_t* o) {
       o->lambda_max_exp10 > 300)
     return fail(SPOTFIT_E_OPTIONS, "lambda exponents not in [-300, 300]");
   if (o->precision != SPOTFIT_PREC_FP32 && o->precision != SPOTFIT_PREC_MIXED &&
-      o->precision != SPOTFIT_PREC_FP64 && o->precision != SPOTFIT_PREC_FP32_PLAIN)
+      o->precision != SPOTFIT_PREC_FP64 && o->precision != SPOTFIT_PREC_FP32_PLAIN &&
+      o->precision != SPOTFIT_PREC_COMP)
     return fail(SPOTFIT_E_OPTIONS, "unknown precision");
   if (!std::isfinite(o->max_error_per_px) || o->max_error_per_px < 0)
     return fail(SPOTFIT_E_OPTIONS, "max_error_per_px must be finite and >= 0");
@@ -204,9 +214,10 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
   c->n_cu = prop.multiProcessorCount;
   const int ppls[5] = {1, 2, 4, 8, 16};
   for (int i = 0; i < 5; ++i) {
-    for (int pr = 0; pr < 2; ++pr) {
+    for (int pr = 0; pr < 3; ++pr) {
+      const int prec = pr == 0 ? SPOTFIT_PREC_FP32 : pr == 1 ? SPOTFIT_PREC_MIXED : SPOTFIT_PREC_COMP;
       int nb = 0;
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sf::wave_kernel_symbol(ppls[i], pr), 64, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sf::wave_kernel_symbol(ppls[i], prec), 64, 0);
       if (e != hipSuccess) {
         delete c;
         return fail_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
@@ -276,7 +287,7 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
   if (const char* env = std::getenv("SPOTFIT_WAVES_PER_CU")) {
     const int v = std::atoi(env);
     if (v > 0 && v <= 64) {
-      for (int i = 0; i < 5; ++i) c->occupancy[i][0] = c->occupancy[i][1] = v;
+      for (int i = 0; i < 5; ++i) c->occupancy[i][0] = c->occupancy[i][1] = c->occupancy[i][2] = v;
       for (int i = 0; i < 16; ++i) c->occ_plan[i] = v;
     }
   }
@@ -455,7 +466,7 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
     e = sf::launch_plain_kernel(ka, threads, (hipStream_t)stream);
   } else {
     const int ppl = sf::ppl_for_pixels(o.max_pixels);
-    const int pr = o.precision == SPOTFIT_PREC_MIXED ? 1 : 0;
+    const int pr = o.precision == SPOTFIT_PREC_MIXED ? 1 : o.precision == SPOTFIT_PREC_COMP ? 2 : 0;
     const int64_t resident = (int64_t)ctx->n_cu * ctx->occupancy[ppl_index(ppl)][pr];
     const int grid = (int)(n < resident ? n : resident);
     e = sf::launch_wave_kernel(ppl, o.precision, ka, grid, (hipStream_t)stream);
@@ -701,6 +712,17 @@ int spotfit_autotune(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
 const char* spotfit_last_error(void) { return g_last_error.c_str(); }
 
 int spotfit_version(void) { return 100; }
+
+int spotfit_exp_neg(const double* x, double* y, int64_t n, void* stream) {
+  if (n < 0) return fail(SPOTFIT_E_ARG, "exp_neg: n < 0");
+  if (n == 0) return SPOTFIT_OK;
+  if (!x || !y) return fail(SPOTFIT_E_NULL, "exp_neg: NULL array");
+  const int64_t blocks = (n + 255) / 256;
+  const int grid = (int)(blocks < 65536 ? blocks : 65536);
+  hipLaunchKernelGGL(exp_neg_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, x, y, n);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPOTFIT_OK : fail_hip(e, "exp_neg launch");
+}
 
 }  // extern "C"
 

@@ -28,8 +28,17 @@
 //               combined by a pairwise tree, D / alpha / beta / derivatives of
 //               the amplitudes / LM solve / residuals and the chi^2 sum in double.
 //   S = float   ("fp32"): everything in single precision, the paper's arithmetic.
+//   S = double, COMP ("comp"): as "mixed", but every per-lane sum of the
+//               evaluations (F, FF, FG and the derivative and normal-equation
+//               sums) is a compensated single-precision sum -- each product's
+//               rounding error recovered with an fma and each addition's with
+//               TwoSum, carried in a second float -- and the lane totals
+//               (sum + error, exact in double) are combined in double.  The
+//               profile and the per-pixel products stay single precision.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "spotfit.h"
 #include "spotfit_internal.h"
@@ -110,6 +119,29 @@ __device__ __forceinline__ void damped_solve(const S (&A)[NP][NP], const S (&b)[
   }
 }
 
+// A single-precision sum with its running rounding error: error-free
+// transformations of the addition (Knuth's TwoSum) and of the product (by fma),
+// as in the compensated dot product of Ogita, Rump and Oishi (SIAM J. Sci.
+// Comput. 26, 2005).  value() = s + c in double.
+struct CSum {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float x) {
+#pragma clang fp contract(off)
+    const float t = s + x;
+    const float z = t - s;
+    c += (s - (t - z)) + (x - z);
+    s = t;
+  }
+  __device__ __forceinline__ void add_prod(float a, float b) {
+#pragma clang fp contract(off)
+    const float p = a * b;
+    const float pe = __builtin_fmaf(a, b, -p);  // a * b - p, exactly
+    add(p);
+    c += pe;
+  }
+  __device__ __forceinline__ double value() const { return double(s) + double(c); }
+};
+
 constexpr float kOffGrid = 4096.0f;  // coordinate of padding lanes: exp(-huge) = 0
 
 template <int PPL>
@@ -140,30 +172,51 @@ struct Np {
 constexpr double kNegHalfLog2e = -0.72134752044448170368;  // -0.5 / ln 2
 
 // Trial evaluation at p: fills f[], returns amplitudes and chi^2 (NaN if D <= 0).
-template <int PPL, int MODEL, typename S>
+template <int PPL, int MODEL, typename S, bool COMP>
 __device__ __forceinline__ AmpState<S> eval_trial(const Pixels<PPL>& px, float (&f)[PPL],
                                                   const S (&p)[Np<MODEL>::v], int N, S G) {
   const S isx2 = S(1) / (p[2] * p[2]);
   const S isy2 = (MODEL == SPOTFIT_SYM) ? isx2 : S(1) / (p[3] * p[3]);
   const S c = S(kNegHalfLog2e);
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int j = 0; j < PPL; ++j) {
-    const S dx = S(px.xs[j]) - p[0];
-    const S dy = S(px.ys[j]) - p[1];
-    const S q = dx * dx * isx2 + dy * dy * isy2;
-    const float e = __builtin_amdgcn_exp2f(float(q * c));
-    f[j] = e;
-    acc[0] += e;
-    acc[1] = __builtin_fmaf(e, e, acc[1]);
-    acc[2] = __builtin_fmaf(e, px.g[j], acc[2]);
-  }
-  float s3[3];
-  wave_sums<4, 3>(acc, s3);
   AmpState<S> st;
-  st.F = S(s3[0]);
-  st.FF = S(s3[1]);
-  st.FG = S(s3[2]);
+  if constexpr (COMP) {
+    CSum cs[3];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const S dx = S(px.xs[j]) - p[0];
+      const S dy = S(px.ys[j]) - p[1];
+      const S q = dx * dx * isx2 + dy * dy * isy2;
+      const float e = __builtin_amdgcn_exp2f(float(q * c));
+      f[j] = e;
+      cs[0].add(e);
+      cs[1].add_prod(e, e);
+      cs[2].add_prod(e, px.g[j]);
+    }
+    double acc[4] = {cs[0].value(), cs[1].value(), cs[2].value(), 0.0};
+    double s3[3];
+    wave_sums<4, 3>(acc, s3);
+    st.F = s3[0];
+    st.FF = s3[1];
+    st.FG = s3[2];
+  } else {
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const S dx = S(px.xs[j]) - p[0];
+      const S dy = S(px.ys[j]) - p[1];
+      const S q = dx * dx * isx2 + dy * dy * isy2;
+      const float e = __builtin_amdgcn_exp2f(float(q * c));
+      f[j] = e;
+      acc[0] += e;
+      acc[1] = __builtin_fmaf(e, e, acc[1]);
+      acc[2] = __builtin_fmaf(e, px.g[j], acc[2]);
+    }
+    float s3[3];
+    wave_sums<4, 3>(acc, s3);
+    st.F = S(s3[0]);
+    st.FF = S(s3[1]);
+    st.FG = S(s3[2]);
+  }
   const S Nn = S(N);
   st.D = Nn * st.FF - st.F * st.F;
   const S nanv = S(__builtin_nan(""));
@@ -211,7 +264,7 @@ struct Pow2Ceil {
 
 // Derivative evaluation at p (f, alpha, beta and sums of the trial evaluation at
 // the same p are reused): normal matrix A and right-hand side b.
-template <int PPL, int MODEL, typename S>
+template <int PPL, int MODEL, typename S, bool COMP>
 __device__ __forceinline__ void eval_grad(const Pixels<PPL>& px, const float (&f)[PPL],
                                           const S (&p)[Np<MODEL>::v], int N, S G,
                                           const AmpState<S>& st, S (&A)[Np<MODEL>::v][Np<MODEL>::v],
@@ -224,24 +277,46 @@ __device__ __forceinline__ void eval_grad(const Pixels<PPL>& px, const float (&f
 
   // round A: dF_j, sum f df_j, dFG_j (Eq. 7)
   constexpr int KA = Pow2Ceil<3 * NP>::v;
-  float acc[KA];
+  using SumT = typename std::conditional<COMP, double, float>::type;
+  SumT sA[3 * NP];
+  if constexpr (COMP) {
+    CSum cs[3 * NP];
 #pragma unroll
-  for (int i = 0; i < KA; ++i) acc[i] = 0.f;
+    for (int j = 0; j < PPL; ++j) {
+      const float dx = float(S(px.xs[j]) - p[0]);
+      const float dy = float(S(px.ys[j]) - p[1]);
+      float df[NP];
+      dprofile<MODEL>(f[j], dx, dy, isxf, isx2f, isyf, isy2f, df);
 #pragma unroll
-  for (int j = 0; j < PPL; ++j) {
-    const float dx = float(S(px.xs[j]) - p[0]);
-    const float dy = float(S(px.ys[j]) - p[1]);
-    float df[NP];
-    dprofile<MODEL>(f[j], dx, dy, isxf, isx2f, isyf, isy2f, df);
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      acc[q] += df[q];
-      acc[NP + q] = __builtin_fmaf(f[j], df[q], acc[NP + q]);
-      acc[2 * NP + q] = __builtin_fmaf(px.g[j], df[q], acc[2 * NP + q]);
+      for (int q = 0; q < NP; ++q) {
+        cs[q].add(df[q]);
+        cs[NP + q].add_prod(f[j], df[q]);
+        cs[2 * NP + q].add_prod(px.g[j], df[q]);
+      }
     }
+    double acc[KA];
+#pragma unroll
+    for (int i = 0; i < KA; ++i) acc[i] = i < 3 * NP ? cs[i].value() : 0.0;
+    wave_sums<KA, 3 * NP>(acc, sA);
+  } else {
+    float acc[KA];
+#pragma unroll
+    for (int i = 0; i < KA; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const float dx = float(S(px.xs[j]) - p[0]);
+      const float dy = float(S(px.ys[j]) - p[1]);
+      float df[NP];
+      dprofile<MODEL>(f[j], dx, dy, isxf, isx2f, isyf, isy2f, df);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        acc[q] += df[q];
+        acc[NP + q] = __builtin_fmaf(f[j], df[q], acc[NP + q]);
+        acc[2 * NP + q] = __builtin_fmaf(px.g[j], df[q], acc[2 * NP + q]);
+      }
+    }
+    wave_sums<KA, 3 * NP>(acc, sA);
   }
-  float sA[3 * NP];
-  wave_sums<KA, 3 * NP>(acc, sA);
 
   // Eq. 8: derivatives of the amplitudes
   const S Nn = S(N);
@@ -259,9 +334,12 @@ __device__ __forceinline__ void eval_grad(const Pixels<PPL>& px, const float (&f
   // round B: J = d r / d p (Eq. 9, second factor), A = J^T J, J^T r
   constexpr int NB = NP * (NP + 1) / 2 + NP;
   constexpr int KB = Pow2Ceil<NB>::v;
-  float bcc[KB];
+  float bcc[COMP ? 1 : KB];
+  CSum bcs[COMP ? NB : 1];
+  if constexpr (!COMP) {
 #pragma unroll
-  for (int i = 0; i < KB; ++i) bcc[i] = 0.f;
+    for (int i = 0; i < KB; ++i) bcc[i] = 0.f;
+  }
   const float af = float(st.a);
   float daf[NP], dbf[NP];
 #pragma unroll
@@ -285,15 +363,30 @@ __device__ __forceinline__ void eval_grad(const Pixels<PPL>& px, const float (&f
     for (int q = 0; q < NP; ++q) {
 #pragma unroll
       for (int u = q; u < NP; ++u) {
-        bcc[t] = __builtin_fmaf(Jk[q], Jk[u], bcc[t]);
+        if constexpr (COMP)
+          bcs[t].add_prod(Jk[q], Jk[u]);
+        else
+          bcc[t] = __builtin_fmaf(Jk[q], Jk[u], bcc[t]);
         ++t;
       }
     }
 #pragma unroll
-    for (int q = 0; q < NP; ++q) bcc[t + q] = __builtin_fmaf(Jk[q], r, bcc[t + q]);
+    for (int q = 0; q < NP; ++q) {
+      if constexpr (COMP)
+        bcs[t + q].add_prod(Jk[q], r);
+      else
+        bcc[t + q] = __builtin_fmaf(Jk[q], r, bcc[t + q]);
+    }
   }
-  float sB[NB];
-  wave_sums<KB, NB>(bcc, sB);
+  SumT sB[NB];
+  if constexpr (COMP) {
+    double acc[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) acc[i] = i < NB ? bcs[i].value() : 0.0;
+    wave_sums<KB, NB>(acc, sB);
+  } else {
+    wave_sums<KB, NB>(bcc, sB);
+  }
   int t = 0;
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
@@ -337,7 +430,7 @@ struct SpotOut {
 };
 
 // The Levenberg-Marquardt loop of one spot (Fit2DGaussian pseudo-code).
-template <int PPL, int MODEL, typename S>
+template <int PPL, int MODEL, typename S, bool COMP>
 __device__ SpotOut lm_fit(const Pixels<PPL>& px, int N, S G, const float* init4, int w, int h,
                           const KOpts& o) {
   constexpr int NP = Np<MODEL>::v;
@@ -356,7 +449,7 @@ __device__ SpotOut lm_fit(const Pixels<PPL>& px, int N, S G, const float* init4,
   int it = 0, status = SPOTFIT_MAX_ITER, n_grad = 0, n_trial = 0;
 
   // state at the current point p
-  AmpState<S> cur = eval_trial<PPL, MODEL, S>(px, f, p, N, G);
+  AmpState<S> cur = eval_trial<PPL, MODEL, S, COMP>(px, f, p, N, G);
   AmpState<S> keep = cur;  // state at best
   S A[NP][NP], bv[NP];
 
@@ -365,7 +458,7 @@ __device__ SpotOut lm_fit(const Pixels<PPL>& px, int N, S G, const float* init4,
     const S chi = cur.chi;
     if (__builtin_isnan(chi)) { status = SPOTFIT_NOT_CONVERGED; break; }
     if (chi < T) { status = SPOTFIT_MAX_ERROR; break; }
-    eval_grad<PPL, MODEL, S>(px, f, p, N, G, cur, A, bv);
+    eval_grad<PPL, MODEL, S, COMP>(px, f, p, N, G, cur, A, bv);
     ++n_grad;
 #pragma unroll
     for (int q = 0; q < NP; ++q) best[q] = p[q];
@@ -375,7 +468,7 @@ __device__ SpotOut lm_fit(const Pixels<PPL>& px, int N, S G, const float* init4,
 #pragma unroll
     for (int q = 0; q < NP; ++q) p[q] = best[q] + delta[q];
     limit_p<MODEL, S>(p, w, h, o);
-    cur = eval_trial<PPL, MODEL, S>(px, f, p, N, G);
+    cur = eval_trial<PPL, MODEL, S, COMP>(px, f, p, N, G);
     ++n_trial;
     if (cur.chi < chi * (S(1) - tau)) --k;  // improved: less damping
 
@@ -386,7 +479,7 @@ __device__ SpotOut lm_fit(const Pixels<PPL>& px, int N, S G, const float* init4,
 #pragma unroll
       for (int q = 0; q < NP; ++q) p[q] = best[q] + delta[q];
       limit_p<MODEL, S>(p, w, h, o);
-      cur = eval_trial<PPL, MODEL, S>(px, f, p, N, G);
+      cur = eval_trial<PPL, MODEL, S, COMP>(px, f, p, N, G);
       ++n_trial;
     }
     if ((chi * (S(1) + tau) < cur.chi) || __builtin_isnan(cur.chi)) {
@@ -450,7 +543,7 @@ __device__ __forceinline__ double load_pixels(Pixels<PPL>& px, const void* data,
   return wave_sum1(gsum);
 }
 
-template <int PPL, typename S>
+template <int PPL, typename S, bool COMP>
 __global__ __launch_bounds__(64) void fit_wave_kernel(KArgs ka) {
   const int lane = lane_id();
   for (int64_t s = blockIdx.x; s < ka.n; s += gridDim.x) {
@@ -477,9 +570,9 @@ __global__ __launch_bounds__(64) void fit_wave_kernel(KArgs ka) {
       Pixels<PPL> px;
       const double G = load_pixels<PPL>(px, ka.data, ka.dtype, ka.offsets[s], w, N);
       if (!ell)
-        out = lm_fit<PPL, SPOTFIT_SYM, S>(px, N, S(G), init4, w, h, ka.opt);
+        out = lm_fit<PPL, SPOTFIT_SYM, S, COMP>(px, N, S(G), init4, w, h, ka.opt);
       else
-        out = lm_fit<PPL, SPOTFIT_ELL, S>(px, N, S(G), init4, w, h, ka.opt);
+        out = lm_fit<PPL, SPOTFIT_ELL, S, COMP>(px, N, S(G), init4, w, h, ka.opt);
     }
     if (lane == 0) {
 #pragma unroll
@@ -498,15 +591,25 @@ __global__ __launch_bounds__(64) void fit_wave_kernel(KArgs ka) {
 // ---------------------------------------------------------------------------
 // Host-side launch table
 // ---------------------------------------------------------------------------
-template <int PPL, typename S>
-static hipError_t launch_one(const KArgs& ka, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((fit_wave_kernel<PPL, S>), dim3(grid), dim3(64), 0, st, ka);
-  return hipGetLastError();
+// precision -> kernel: FP32 (float), MIXED (double), COMP (double, compensated sums)
+template <int PPL>
+static const void* kernel_ptr(int precision) {
+  if (precision == SPOTFIT_PREC_MIXED)
+    return reinterpret_cast<const void*>(&fit_wave_kernel<PPL, double, false>);
+  if (precision == SPOTFIT_PREC_COMP)
+    return reinterpret_cast<const void*>(&fit_wave_kernel<PPL, double, true>);
+  return reinterpret_cast<const void*>(&fit_wave_kernel<PPL, float, false>);
 }
 
-template <int PPL, typename S>
-static const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&fit_wave_kernel<PPL, S>);
+template <int PPL>
+static hipError_t launch_one(int precision, const KArgs& ka, int grid, hipStream_t st) {
+  if (precision == SPOTFIT_PREC_MIXED)
+    hipLaunchKernelGGL((fit_wave_kernel<PPL, double, false>), dim3(grid), dim3(64), 0, st, ka);
+  else if (precision == SPOTFIT_PREC_COMP)
+    hipLaunchKernelGGL((fit_wave_kernel<PPL, double, true>), dim3(grid), dim3(64), 0, st, ka);
+  else
+    hipLaunchKernelGGL((fit_wave_kernel<PPL, float, false>), dim3(grid), dim3(64), 0, st, ka);
+  return hipGetLastError();
 }
 
 int ppl_for_pixels(int max_pixels) {
@@ -519,25 +622,22 @@ int ppl_for_pixels(int max_pixels) {
 }
 
 const void* wave_kernel_symbol(int ppl, int precision) {
-  const bool dbl = precision == SPOTFIT_PREC_MIXED;
   switch (ppl) {
-    case 1: return dbl ? kernel_ptr<1, double>() : kernel_ptr<1, float>();
-    case 2: return dbl ? kernel_ptr<2, double>() : kernel_ptr<2, float>();
-    case 4: return dbl ? kernel_ptr<4, double>() : kernel_ptr<4, float>();
-    case 8: return dbl ? kernel_ptr<8, double>() : kernel_ptr<8, float>();
-    default: return dbl ? kernel_ptr<16, double>() : kernel_ptr<16, float>();
+    case 1: return kernel_ptr<1>(precision);
+    case 2: return kernel_ptr<2>(precision);
+    case 4: return kernel_ptr<4>(precision);
+    case 8: return kernel_ptr<8>(precision);
+    default: return kernel_ptr<16>(precision);
   }
 }
 
 hipError_t launch_wave_kernel(int ppl, int precision, const KArgs& ka, int grid, hipStream_t st) {
-  const bool dbl = precision == SPOTFIT_PREC_MIXED;
   switch (ppl) {
-    case 1: return dbl ? launch_one<1, double>(ka, grid, st) : launch_one<1, float>(ka, grid, st);
-    case 2: return dbl ? launch_one<2, double>(ka, grid, st) : launch_one<2, float>(ka, grid, st);
-    case 4: return dbl ? launch_one<4, double>(ka, grid, st) : launch_one<4, float>(ka, grid, st);
-    case 8: return dbl ? launch_one<8, double>(ka, grid, st) : launch_one<8, float>(ka, grid, st);
-    default:
-      return dbl ? launch_one<16, double>(ka, grid, st) : launch_one<16, float>(ka, grid, st);
+    case 1: return launch_one<1>(precision, ka, grid, st);
+    case 2: return launch_one<2>(precision, ka, grid, st);
+    case 4: return launch_one<4>(precision, ka, grid, st);
+    case 8: return launch_one<8>(precision, ka, grid, st);
+    default: return launch_one<16>(precision, ka, grid, st);
   }
 }
 

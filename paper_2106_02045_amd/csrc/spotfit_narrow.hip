@@ -10,8 +10,9 @@
 //  * Lane l of a group owns the columns c = l + L*j (j < CPL) with all their
 //    rows: the CPL*HM raw pixel values stay in registers for the whole fit and
 //    are converted where used.  It computes ex(c) for its columns and ey(r)
-//    for the rows r = l + L*j; every lane then gathers all HM row factors from
-//    its group by DPP (or ds_swizzle) broadcasts.
+//    for the rows r = l + L*j; a pass over the pixels fetches each row's factor
+//    from the lane that holds it by a DPP (or ds_swizzle) broadcast when it
+//    reaches the row.
 //  * The per-spot scalar state is identical on the L lanes: each lane takes
 //    every scalar step itself, and the iteration state lives in LDS, each lane
 //    reading back only its own writes, so no barriers are needed.
@@ -46,13 +47,18 @@ namespace nrw {
 using namespace lm;
 using namespace lg;
 
-// all[Q + L*j] = own[j] of in-group lane Q, for every Q < L.
-template <int L, int Q, int CPL, int HM>
-__device__ __forceinline__ void gather_rows(const double (&own)[CPL], double (&all)[HM]) {
-  if constexpr (Q < L) {
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) all[Q + L * j] = gbcast<L, Q>(own[j]);
-    gather_rows<L, Q + 1>(own, all);
+// Row factor of row r (held by in-group lane r % L as its own[r / L]) on every
+// lane of the group.
+template <int L, int CPL, int R>
+__device__ __forceinline__ double row_factor(const double (&own)[CPL]) {
+  return gbcast<L, R % L>(own[R / L]);
+}
+
+template <int L, int CPL, int HM, int R = 0, typename F>
+__device__ __forceinline__ void for_rows(const double (&own)[CPL], F&& f) {
+  if constexpr (R < HM) {
+    f(R, row_factor<L, CPL, R>(own));
+    for_rows<L, CPL, HM, R + 1>(own, f);
   }
 }
 
@@ -371,19 +377,16 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
           syp += eyl[j];
           syyp = __builtin_fma(eyl[j], eyl[j], syyp);
         }
-        double ey[HM];
-        gather_rows<L, 0>(eyl, ey);
         // column sums t(c) = sum_r g ey and row sums s(r) = sum_c g ex (lane's columns);
-        // **G** = sum_r ey s(r), and the row-weighted forms of the derivative pass
+        // **G** = sum_r ey s(r), and the row-weighted forms of the derivative pass;
+        // each row factor is fetched from its lane when its row is reached
         double t[CPL];
 #pragma unroll
         for (int j = 0; j < CPL; ++j) t[j] = 0.0;
         double gp = 0.0, byp = 0.0, bsyp = 0.0, gsum_px = 0.0, ggp = 0.0;
         uint32_t gsi = 0;
-#pragma unroll
-        for (int r = 0; r < HM; ++r) {
+        for_rows<L, CPL, HM>(eyl, [&](int r, double e) {
           if (r < h) {
-            const double e = ey[r];
             double sr = 0.0;
 #pragma unroll
             for (int j = 0; j < CPL; ++j) {
@@ -404,7 +407,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
             byp = __builtin_fma(double(r), es, byp);
             bsyp = __builtin_fma(double(r * r), es, bsyp);
           }
-        }
+        });
         double bxp = 0.0, bsxp = 0.0;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
@@ -469,10 +472,8 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
             bm[j] = li + L * j < w ? b : 0.0;
             c2[j] = 0.0;
           }
-#pragma unroll
-          for (int r = 0; r < HM; ++r) {
+          for_rows<L, CPL, HM>(eyl, [&](int r, double e) {
             if (r < h) {
-              const double e = ey[r];
 #pragma unroll
               for (int j = 0; j < CPL; ++j) {
                 // a fresh conversion: reusing the first pass's doubles would keep
@@ -483,7 +484,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
                 c2[j] = __builtin_fma(res, res, c2[j]);
               }
             }
-          }
+          });
           double c2s = c2[0];
 #pragma unroll
           for (int j = 1; j < CPL; ++j) c2s += c2[j];
