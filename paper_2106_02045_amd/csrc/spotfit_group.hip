@@ -239,12 +239,22 @@ __device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * 
         const double hx = -0.5 * rcp_nr(S.pc[2] * S.pc[2]);
         const double hy = -0.5 * rcp_nr(S.pc[3] * S.pc[3]);
         double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        // the lane's 2 CPL factors at once (outside the spot too, then dropped):
+        // their exponentials interleave instead of running one after another
+        double arg[2 * CPL], fac[2 * CPL];
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
           const int c = li + L * j;
           const double dxc = double(c) - x, dyr = double(c) - y;
-          ex[j] = c < w ? exp(dxc * dxc * hx) : 0.0;
-          eyo[j] = c < h ? exp(dyr * dyr * hy) : 0.0;
+          arg[j] = dxc * dxc * hx;
+          arg[CPL + j] = dyr * dyr * hy;
+        }
+        exp_neg_n<2 * CPL>(arg, fac);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int c = li + L * j;
+          ex[j] = c < w ? fac[j] : 0.0;
+          eyo[j] = c < h ? fac[CPL + j] : 0.0;
           S.ey[c] = eyo[j];
           v[0] += ex[j];
           v[1] = __builtin_fma(ex[j], ex[j], v[1]);

@@ -123,5 +123,40 @@ __device__ __forceinline__ double exp_neg(double x) {
   return __builtin_ldexp(p, (int)n);
 }
 
+// e^x[i] for N independent arguments x[i] <= 0 (each as exp_neg), with the
+// steps of the N evaluations interleaved: the multiply-adds of different
+// arguments are independent, so N of them are in flight together instead of
+// one dependent chain of 13 after another.
+template <int N>
+__device__ __forceinline__ void exp_neg_n(const double (&x)[N], double (&y)[N]) {
+  constexpr double kLog2e = 1.4426950408889634;
+  constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;
+  constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;
+  constexpr double kC[11] = {1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0,
+                             1.0 / 362880.0,    1.0 / 40320.0,    1.0 / 5040.0,
+                             1.0 / 720.0,       1.0 / 120.0,      1.0 / 24.0,
+                             1.0 / 6.0,         0.5};  // 1/k!, k = 12 .. 2
+  double n[N], r[N], p[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    n[i] = __builtin_rint(x[i] * kLog2e);
+    r[i] = __builtin_fma(-n[i], kLn2Hi, x[i]);
+    r[i] = __builtin_fma(-n[i], kLn2Lo, r[i]);
+    p[i] = 1.0 / 6227020800.0;  // 1/13!
+  }
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i] = fma_s(p[i], r[i], kC[k]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    p[i] = __builtin_fma(p[i], r[i], kC[10]);
+    p[i] = __builtin_fma(p[i], r[i], 1.0);
+    p[i] = __builtin_fma(p[i], r[i], 1.0);
+    y[i] = __builtin_ldexp(p[i], (int)n[i]);
+  }
+}
+
 }  // namespace lm
 }  // namespace sf

@@ -315,11 +315,16 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
 #pragma unroll
       for (int j = 0; j < CPL; ++j)
         cp[j] = li + L * j < w ? static_cast<const uint16_t*>(ka.data) + off + li + L * j : zero;
+      // row offsets in bytes by additions (no multiply per row): rows below the
+      // spot stay on its last row
+      const uint32_t step = 2u * uint32_t(w), last = uint32_t(hh - 1) * step;
+      uint32_t rb = 0;
 #pragma unroll
       for (int r = 0; r < HM; ++r) {
-        const uint32_t ro = uint32_t(r < hh ? r : hh - 1) * uint32_t(w);
+        if (r > 0) rb = __builtin_elementwise_min(rb + step, last);
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) g[j][r] = cp[j][ro];
+        for (int j = 0; j < CPL; ++j)
+          g[j][r] = *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(cp[j]) + rb);
       }
     } else {
       const uint32_t* zero = reinterpret_cast<const uint32_t*>(kZeros);
@@ -327,11 +332,14 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
 #pragma unroll
       for (int j = 0; j < CPL; ++j)
         cp[j] = li + L * j < w ? static_cast<const uint32_t*>(ka.data) + off + li + L * j : zero;
+      const uint32_t step = 4u * uint32_t(w), last = uint32_t(hh - 1) * step;
+      uint32_t rb = 0;
 #pragma unroll
       for (int r = 0; r < HM; ++r) {
-        const uint32_t ro = uint32_t(r < hh ? r : hh - 1) * uint32_t(w);
+        if (r > 0) rb = __builtin_elementwise_min(rb + step, last);
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) g[j][r] = cp[j][ro];
+        for (int j = 0; j < CPL; ++j)
+          g[j][r] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(cp[j]) + rb);
       }
     }
   };
@@ -366,12 +374,22 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         const double hx = -0.5 * rcp_nr(pc[2] * pc[2]);
         const double hy = -0.5 * rcp_nr(pc[3] * pc[3]);
         double sxp = 0.0, sxxp = 0.0, syp = 0.0, syyp = 0.0;
+        // all 2 CPL factors at once, outside the spot too (then dropped), so
+        // that their exponentials interleave instead of running one by one
+        double arg[2 * CPL], fac[2 * CPL];
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
           const int c = li + L * j;
           const double dxc = double(c) - x, dyr = double(c) - y;
-          ex[j] = c < w ? exp_neg(dxc * dxc * hx) : 0.0;
-          eyl[j] = c < h ? exp_neg(dyr * dyr * hy) : 0.0;
+          arg[j] = dxc * dxc * hx;
+          arg[CPL + j] = dyr * dyr * hy;
+        }
+        exp_neg_n<2 * CPL>(arg, fac);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int c = li + L * j;
+          ex[j] = c < w ? fac[j] : 0.0;
+          eyl[j] = c < h ? fac[CPL + j] : 0.0;
           sxp += ex[j];
           sxxp = __builtin_fma(ex[j], ex[j], sxxp);
           syp += eyl[j];
