@@ -401,6 +401,9 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   ka.opt.min_delta = o.min_delta;
   ka.opt.min_step_rel = o.min_step_rel;
   ka.opt.tie_tau = o.tie_tau;
+  ka.opt.one_minus_tau = 1.0 - o.tie_tau;
+  ka.opt.one_plus_tau = 1.0 + o.tie_tau;
+  ka.opt.one_minus_min_delta = 1.0 - o.min_delta;
   ka.opt.sigma_min = o.sigma_min;
   ka.opt.sigma_max_frac = o.sigma_max_frac;
 

@@ -130,7 +130,6 @@ __device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * 
   const int li = lane % L;
   State<HM>& S = sts[gi];
   const KOpts o = ka.opt;
-  const double tau = o.tie_tau;
 
   // ---- per-group control state (identical on the L lanes of a group) ----
   int64_t s = src.first(gi, li, S.next);
@@ -351,7 +350,7 @@ __device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * 
         start = true;
       } else {
         const double Chi = S.chi, chi = S.chi_best;
-        if (mode == kTrialFirst && Chi < chi * (1.0 - tau)) --k;  // improved: less damping
+        if (mode == kTrialFirst && Chi < chi * o.one_minus_tau) --k;  // improved: less damping
         // MinStep: every step below min_step_rel of its parameter, the centre
         // measured from the centre of the ROI
         bool small = true;
@@ -361,7 +360,7 @@ __device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * 
           small = small &&
                   ((sym && q == 3) || fabs(S.delta[q]) < o.min_step_rel * fabs(S.best[q] - org));
         }
-        const bool worse = chi * (1.0 + tau) < Chi;
+        const bool worse = chi * o.one_plus_tau < Chi;
         if (!small && worse && k < o.lambda_max_exp10) {
           ++k;  // more damping, retry from best
           mode = kTrialRetry;
@@ -380,7 +379,7 @@ __device__ __forceinline__ void fit_groups(const KArgs& ka, Src& src, State<L * 
           if (Chi < S.Tme) {
             status = SPOTFIT_MAX_ERROR;
             done = true;
-          } else if (chi * (1.0 - o.min_delta) < Chi) {
+          } else if (chi * o.one_minus_min_delta < Chi) {
             status = SPOTFIT_MIN_DELTA;
             done = true;
           } else if (small) {

@@ -22,6 +22,13 @@ struct KOpts {
   double tie_tau;
   double sigma_min;
   double sigma_max_frac;
+  // the comparison factors of the loop's decisions, formed once on the host
+  // (the same double roundings as on the device): kernel arguments live in
+  // scalar registers, whereas loop invariants formed in the kernel take vector
+  // registers for the whole fit
+  double one_minus_tau;        // 1 - tie_tau
+  double one_plus_tau;         // 1 + tie_tau
+  double one_minus_min_delta;  // 1 - min_delta
 };
 
 // Kernel arguments of one fit launch (all pointers are device memory).

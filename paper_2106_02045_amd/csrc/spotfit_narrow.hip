@@ -140,7 +140,6 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
   const int gi = lane / L;
   const int li = lane % L;
   const KOpts o = ka.opt;
-  const double tau = o.tie_tau;
 
   int64_t s = -1;  // the group's current spot
   int w = 0, h = 0, k = 0, it = 0, status = 0, mode = kNew, n_grad = 0, n_trial = 0;
@@ -536,8 +535,9 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         bool near_self = fabs(chi - Tme) <= chi_err, near_best = false;
         if (mode != kNew) {
           const double e2 = chi_err + eb;
-          near_best = fabs(chi - chib * (1.0 - tau)) <= e2 || fabs(chi - chib * (1.0 + tau)) <= e2 ||
-                      fabs(chi - chib * (1.0 - o.min_delta)) <= e2;
+          near_best = fabs(chi - chib * o.one_minus_tau) <= e2 ||
+                      fabs(chi - chib * o.one_plus_tau) <= e2 ||
+                      fabs(chi - chib * o.one_minus_min_delta) <= e2;
         }
         if (near_self || near_best) {
           S.mode_saved = mode;
@@ -559,8 +559,8 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         start = true;
       } else {
         const double Chi = chi, chib = S.chi_best;
-        if (mode == kTrialFirst && Chi < chib * (1.0 - tau)) --k;  // improved: less damping
-        const bool worse = chib * (1.0 + tau) < Chi;
+        if (mode == kTrialFirst && Chi < chib * o.one_minus_tau) --k;  // improved: less damping
+        const bool worse = chib * o.one_plus_tau < Chi;
         if (!small && worse && k < o.lambda_max_exp10) {
           ++k;  // more damping, retry from best
           mode = kTrialRetry;
@@ -572,7 +572,7 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         } else if (Chi < Tme) {
           status = SPOTFIT_MAX_ERROR;
           done = true;
-        } else if (chib * (1.0 - o.min_delta) < Chi) {
+        } else if (chib * o.one_minus_min_delta < Chi) {
           status = SPOTFIT_MIN_DELTA;
           done = true;
         } else if (small) {
@@ -725,7 +725,11 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
           S.A[6] = 0.0;
           S.A[7] += 2.0 * S.A[8] + S.A[9];
           S.A[8] = 0.0;
-          S.A[9] = 1.0;
+          // 1.0 made here: held across the loop instead, it is a register the
+          // allocator spills when the mixed launch inlines three class loops
+          double one;
+          asm volatile("v_mov_b64 %0, 1.0" : "=v"(one));
+          S.A[9] = one;
           S.bv[2] += S.bv[3];
           S.bv[3] = 0.0;
         }
@@ -820,9 +824,11 @@ const void* narrow_kernel_symbol(int plan) {
 
 // Mixed-size plans (size classes <= 8, <= 16, <= 32 px side): lanes and columns
 // per class, min waves per SIMD.
-#define SF_NARROW_MIXED_PLANS(X) X(0, 4, 2, 4, 4, 16, 2, 2)
+#define SF_NARROW_MIXED_PLANS(X) \
+  X(0, 4, 2, 4, 4, 16, 2, 2)       \
+  X(1, 4, 2, 8, 2, 16, 2, 2)
 
-int narrow_mixed_plan_count() { return 1; }
+int narrow_mixed_plan_count() { return 2; }
 
 const void* narrow_mixed_kernel_symbol(int plan) {
 #define SF_NMSYM(I, A, B, C, D, E, F, W) \
