@@ -172,7 +172,7 @@ int spotfit_ctx_create(spotfit_ctx_t** ctx, int device);
 void spotfit_ctx_destroy(spotfit_ctx_t* ctx);
 
 /* Size the context's device workspace for mixed-schedule calls of up to n_spots
- * spots (12 bytes per spot plus 32 bytes).  A mixed-schedule call with more spots
+ * spots (12 bytes per spot plus 544 bytes).  A mixed-schedule call with more spots
  * than reserved grows the workspace itself (one synchronous device allocation),
  * so callers that must not allocate inside a call (graph capture, serving loops)
  * reserve first.  Returns SPOTFIT_OK, SPOTFIT_E_NULL, SPOTFIT_E_ARG or
@@ -196,7 +196,7 @@ int spotfit_fit_spots(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
  * context and options), but the fit's scratch memory -- the spot counter of
  * the uniform schedule, the counters and size-class lists of the mixed
  * schedule -- is a fixed array of the library in device memory instead of the
- * context's workspace.  The array is 4 * (72 + 3 * SPOTFIT_NOALLOC_MAX_SPOTS)
+ * context's workspace.  The array is 4 * (200 + 3 * SPOTFIT_NOALLOC_MAX_SPOTS)
  * bytes (about 12.6 MB) on every GPU the library runs on, held until the
  * process ends; its address on a device is looked up when the first context
  * on that device is created.  The call allocates nothing and never grows the

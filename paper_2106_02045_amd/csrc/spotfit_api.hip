@@ -37,13 +37,14 @@ struct spotfit_ctx {
 };
 
 // Scratch memory of spotfit_fit_spots_noalloc: word 0 the uniform schedule's
-// spot counter; from word 64 (256 bytes in) the mixed schedule's 8 counters and
-// its 3 size-class lists of SPOTFIT_NOALLOC_MAX_SPOTS spot indices.  Every GPU
+// spot counter; from word 64 (256 bytes in) the mixed schedule's workspace: 8
+// counters, the classify pass's 128 words, then its 3 size-class lists of
+// SPOTFIT_NOALLOC_MAX_SPOTS spot indices.  Every GPU
 // holds its own copy at its own address.  In host code this name only stands
 // for the array: kernels get the address that hipGetSymbolAddress returns for
 // the current device (kept per device in g_scratch_addr and in each context).
 constexpr int64_t kScratchMixedAt = 64;
-constexpr int64_t kScratchWords = kScratchMixedAt + 8 + 3 * (int64_t)SPOTFIT_NOALLOC_MAX_SPOTS;
+constexpr int64_t kScratchWords = kScratchMixedAt + sf::kMixedHeadWords + 3 * (int64_t)SPOTFIT_NOALLOC_MAX_SPOTS;
 static __device__ __align__(256) int32_t scratch[kScratchWords];
 
 namespace {
@@ -325,7 +326,7 @@ int spotfit_ctx_reserve(spotfit_ctx_t* ctx, int64_t n) {
     ctx->ws_cap = 0;
   }
   int32_t* p = nullptr;
-  if (e == hipSuccess) e = hipMalloc((void**)&p, sizeof(int32_t) * (size_t)(8 + 3 * n));
+  if (e == hipSuccess) e = hipMalloc((void**)&p, sizeof(int32_t) * (size_t)(sf::kMixedHeadWords + 3 * n));
   if (cur != ctx->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) return fail_hip(e, "hipMalloc (mixed workspace)");
   ctx->ws = p;
@@ -415,7 +416,8 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
     }
     const sf::MixedWs ws = classified ? *classified
                            : own_ws   ? *own_ws
-                                      : sf::MixedWs{ctx->ws, ctx->ws + 8, ctx->ws_cap};
+                                      : sf::MixedWs{ctx->ws, ctx->ws + sf::kMixedHeadWords, ctx->ws_cap,
+                                                    ctx->ws + 8};
     // latency: the wide mixed-size plan (8, 16, 32 lanes per spot); up to
     // kLeanMaxSpots spots its one-wave-per-SIMD build, which spills no
     // registers (those batches leave most of the chip idle anyway)
@@ -545,8 +547,9 @@ int spotfit_fit_spots_noalloc(spotfit_ctx_t* ctx, const void* data, int32_t dtyp
   if (!ctx->scratch) return fail(SPOTFIT_E_DEVICE, "fit_spots_noalloc: no scratch address");
   // the counters and lists live in this device's copy of `scratch`; the
   // kernels that use them clear the counters first (no memset, no allocation)
-  const sf::MixedWs ws{ctx->scratch + kScratchMixedAt, ctx->scratch + kScratchMixedAt + 8,
-                       (int64_t)SPOTFIT_NOALLOC_MAX_SPOTS};
+  const sf::MixedWs ws{ctx->scratch + kScratchMixedAt,
+                       ctx->scratch + kScratchMixedAt + sf::kMixedHeadWords,
+                       (int64_t)SPOTFIT_NOALLOC_MAX_SPOTS, ctx->scratch + kScratchMixedAt + 8};
   return launch_fit(ctx, data, dtype, sizes, offsets, init, n, o, params_out, chi2_out, iters_out,
                     status_out, evals_out, stream, nullptr, nullptr, &ws, ctx->scratch);
 }
@@ -781,13 +784,13 @@ int spotfit_graph_create(spotfit_graph_t** out, spotfit_ctx_t* ctx, const void* 
   const bool mixed = o.precision == SPOTFIT_PREC_FP64 && o.schedule == SPOTFIT_SCHEDULE_MIXED;
   sf::MixedWs gws{nullptr, nullptr, 0};
   if (mixed) {
-    e = hipMalloc((void**)&g->ws, sizeof(int32_t) * (size_t)(8 + 3 * n));
+    e = hipMalloc((void**)&g->ws, sizeof(int32_t) * (size_t)(sf::kMixedHeadWords + 3 * n));
     if (e != hipSuccess) {
       g->ws = nullptr;
       spotfit_graph_destroy(g);
       return fail_hip(e, "hipMalloc (graph workspace)");
     }
-    gws = sf::MixedWs{g->ws, g->ws + 8, n};
+    gws = sf::MixedWs{g->ws, g->ws + sf::kMixedHeadWords, n, g->ws + 8};
   }
   if (raw) {
     e = hipMalloc((void**)&g->init_buf, sizeof(float) * 4 * (size_t)n);

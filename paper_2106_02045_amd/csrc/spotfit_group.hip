@@ -615,50 +615,82 @@ __device__ __forceinline__ int size_class(const spotfit_shape_t& sh) {
   return m <= 8 ? 0 : m <= 16 ? 1 : 2;
 }
 
+__device__ __forceinline__ int side_bucket(const spotfit_shape_t& sh) {
+  const int m = sh.w > sh.h ? sh.w : sh.h;
+  return m < kSortBuckets - 1 ? m : kSortBuckets - 1;
+}
+
+__device__ __forceinline__ int bucket_class(int b) { return b <= 8 ? 0 : b <= 16 ? 1 : 2; }
+
+// Where each side's spots start in their class's list (buckets in increasing
+// side), and the class totals: one thread.
+__device__ __forceinline__ void bucket_offsets(const int* cnt, int* cursor, int32_t* counters) {
+  int tot[3] = {0, 0, 0};
+  for (int b = 0; b < kSortBuckets; ++b) {
+    const int c = bucket_class(b);
+    cursor[b] = tot[c];
+    tot[c] += cnt[b];
+  }
+  for (int c = 0; c < 3; ++c) counters[c] = tot[c];
+}
+
 __global__ void mixed_reset_kernel(MixedWs ws) {
   if (threadIdx.x < 8) ws.counters[threadIdx.x] = 0;
+  if (threadIdx.x < kSortWords) ws.sort[threadIdx.x] = 0;
 }
 
-// Small batches (serving frames): zero the counters and classify in one
-// workgroup, one launch instead of two.
+// Small batches (serving frames): the whole counting sort in one workgroup
+// (counts, offsets and the scatter in LDS), one launch.
 __global__ __launch_bounds__(1024) void mixed_small_classify_kernel(const spotfit_shape_t* sizes,
                                                                     int64_t n, MixedWs ws) {
+  __shared__ int cnt[kSortBuckets], cursor[kSortBuckets];
   if (threadIdx.x < 8) ws.counters[threadIdx.x] = 0;
+  if (threadIdx.x < kSortBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int lane = __lane_id();
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t b = 0; b < n; b += blockDim.x) {
-    const int64_t s = b + threadIdx.x;
-    const int cls = s < n ? size_class(sizes[s]) : -1;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const uint64_t mask = __builtin_amdgcn_ballot_w64(cls == c);
-      if (mask == 0) continue;
-      const int leader = __builtin_ctzll(mask);
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&ws.counters[c], (int)__builtin_popcountll(mask));
-      base = __builtin_amdgcn_readlane(base, leader);
-      if (cls == c) ws.lists[(int64_t)c * ws.cap + base + __builtin_popcountll(mask & below)] = (int32_t)s;
-    }
+  for (int64_t s = threadIdx.x; s < n; s += blockDim.x) atomicAdd(&cnt[side_bucket(sizes[s])], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) bucket_offsets(cnt, cursor, ws.counters);
+  __syncthreads();
+  for (int64_t s = threadIdx.x; s < n; s += blockDim.x) {
+    const int b = side_bucket(sizes[s]);
+    const int pos = atomicAdd(&cursor[b], 1);
+    ws.lists[(int64_t)bucket_class(b) * ws.cap + pos] = (int32_t)s;
   }
 }
 
-__global__ __launch_bounds__(256) void mixed_classify_kernel(const spotfit_shape_t* sizes, int64_t n,
-                                                             MixedWs ws) {
+// Large batches, pass 1: spots per larger side (block histograms in LDS).
+__global__ __launch_bounds__(256) void mixed_count_kernel(const spotfit_shape_t* sizes, int64_t n,
+                                                         MixedWs ws) {
+  __shared__ int cnt[kSortBuckets];
+  if (threadIdx.x < kSortBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int cls = s < n ? size_class(sizes[s]) : -1;
-  const int lane = __lane_id();
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const uint64_t mask = __builtin_amdgcn_ballot_w64(cls == c);
-    if (mask == 0) continue;
-    const int leader = __builtin_ctzll(mask);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&ws.counters[c], (int)__builtin_popcountll(mask));
-    base = __builtin_amdgcn_readlane(base, leader);
-    if (cls == c) ws.lists[(int64_t)c * ws.cap + base + __builtin_popcountll(mask & below)] = (int32_t)s;
-  }
+  if (s < n) atomicAdd(&cnt[side_bucket(sizes[s])], 1);
+  __syncthreads();
+  if (threadIdx.x < kSortBuckets && cnt[threadIdx.x])
+    atomicAdd(&ws.sort[threadIdx.x], cnt[threadIdx.x]);
+}
+
+// Pass 2: list offsets of the sides and class totals.
+__global__ void mixed_offsets_kernel(MixedWs ws) {
+  if (threadIdx.x == 0) bucket_offsets(ws.sort, ws.sort + 64, ws.counters);
+}
+
+// Pass 3: each block reserves a range of every side's part of the list and
+// writes its spots there.
+__global__ __launch_bounds__(256) void mixed_scatter_kernel(const spotfit_shape_t* sizes, int64_t n,
+                                                           MixedWs ws) {
+  __shared__ int cnt[kSortBuckets], base[kSortBuckets];
+  if (threadIdx.x < kSortBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = s < n ? side_bucket(sizes[s]) : 0;
+  const int rank = s < n ? atomicAdd(&cnt[b], 1) : 0;
+  __syncthreads();
+  if (threadIdx.x < kSortBuckets && cnt[threadIdx.x])
+    base[threadIdx.x] = atomicAdd(&ws.sort[64 + threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+  if (s < n) ws.lists[(int64_t)bucket_class(b) * ws.cap + base[b] + rank] = (int32_t)s;
 }
 
 template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE, bool RAW>
@@ -781,17 +813,28 @@ const void* mixed_kernel_symbol(int plan) {
 
 hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, hipStream_t st) {
   hipError_t e;
+  if (!ws.sort) return hipErrorInvalidValue;
   if (ka.n <= 65536) {
     hipLaunchKernelGGL(grp::mixed_small_classify_kernel, dim3(1), dim3(1024), 0, st, ka.sizes, ka.n, ws);
     e = hipGetLastError();
   } else {
-    hipLaunchKernelGGL(grp::mixed_reset_kernel, dim3(1), dim3(64), 0, st, ws);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const int64_t cb = (ka.n + 255) / 256;
-    hipLaunchKernelGGL(grp::mixed_classify_kernel, dim3((unsigned)cb), dim3(256), 0, st, ka.sizes,
-                       ka.n, ws);
+    hipLaunchKernelGGL(grp::mixed_reset_kernel, dim3(1), dim3(kSortWords), 0, st, ws);
     e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(grp::mixed_count_kernel, dim3((unsigned)cb), dim3(256), 0, st, ka.sizes,
+                         ka.n, ws);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(grp::mixed_offsets_kernel, dim3(1), dim3(64), 0, st, ws);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(grp::mixed_scatter_kernel, dim3((unsigned)cb), dim3(256), 0, st, ka.sizes,
+                         ka.n, ws);
+      e = hipGetLastError();
+    }
   }
   if (e != hipSuccess) return e;
   return launch_mixed_fit(plan, ka, ws, grid, st);

@@ -59,12 +59,23 @@ hipError_t launch_wave_kernel(int ppl, int precision, const KArgs& ka, int grid,
 hipError_t launch_plain_kernel(const KArgs& ka, int threads, hipStream_t st);
 
 // Device workspace of mixed-size batches: counters[0..2] spots per size class,
-// counters[3..5] spots taken; lists: 3 regions of `cap` spot indices.
+// counters[3..5] spots taken; lists: 3 regions of `cap` spot indices.  The
+// classify pass orders each class's list by the spots' larger side (a counting
+// sort: `sort` holds its per-side counts and cursors), so that the groups of a
+// wavefront mostly hold spots of one size and its row loops stop at their
+// height; lists built elsewhere may be in any order (sort is then unused).
 struct MixedWs {
   int32_t* counters;
   int32_t* lists;
   int64_t cap;
+  int32_t* sort = nullptr;
 };
+// Words of a mixed workspace before its lists: 8 counters, then kSortWords for
+// the classify pass's counts (larger side 0..32, and 33 for anything above) and
+// cursors.
+constexpr int kSortBuckets = 34;
+constexpr int kSortWords = 128;
+constexpr int64_t kMixedHeadWords = 8 + kSortWords;
 
 // Mixed-size batches: reset + classify + one persistent fit launch.
 int mixed_plan_count();
