@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["spotfit_kernels.hip", "spotfit_group.hip", "spotfit_narrow.hip", "spotfit_init.hip",
-           "spotfit_plain.hip", "spotfit_api.hip",
+           "spotfit_plain.hip", "spotfit_owned.hip", "spotfit_api.hip",
            "spotfit_serve.hip", "spotfit_track.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 OUT = os.path.join(HERE, "libspotfit.so")

@@ -267,10 +267,11 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
     delete c;
     return fail_hip(e, "hipMalloc (context buffers)");
   }
-  // default plan per size class (measured on MI355X), all narrow: <= 8 px side:
-  // 4 lanes x 2 columns; <= 16: 4 lanes x 4 columns; <= 32: 16 lanes x 2 columns
+  // default plan per size class (measured on MI355X): <= 8 px side: narrow, 4
+  // lanes x 2 columns; <= 16: lane-owned (4-lane groups of 4 spots, 4 columns
+  // per lane); <= 32: narrow, 16 lanes x 2 columns
   c->plan_for_class[0] = sf::wide_plan_count() + 0;
-  c->plan_for_class[1] = sf::wide_plan_count() + 1;
+  c->plan_for_class[1] = sf::owned_plan_id();
   c->plan_for_class[2] = sf::wide_plan_count() + 3;
   if (const char* env = std::getenv("SPOTFIT_GROUP_PLAN")) {
     // tuning override "a,b,c": plan for each size class
@@ -434,8 +435,10 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
     // builds of 16x1 and 32x1 that spill no registers for batches that they hold
     // resident at once (measured: up to 5-10 % faster there, 10-35 % slower at
     // several resident rounds)
-    const int wide_for_class[3] = {0, 2, 4}, lean_for_class[3] = {0, 9, 10};
+    const int one_wave = sf::wide_plan_count() + sf::narrow_plan_count();
+    const int wide_for_class[3] = {0, 2, 4}, lean_for_class[3] = {0, one_wave, one_wave + 1};
     int plan = ctx->plan_for_class[cls];
+    if (init_out) plan = sf::plan_for_raw(plan);
     int lanes = 0, cpl = 0;
     if (o.plan_hint == SPOTFIT_PLAN_LATENCY) {
       plan = wide_for_class[cls];

@@ -746,9 +746,12 @@ static const void* sym_lw() {
 
 int wide_plan_count() { return 5; }
 
-int group_plan_count() { return wide_plan_count() + narrow_plan_count() + 2; }
+int group_plan_count() { return wide_plan_count() + narrow_plan_count() + 3; }
 
-// Plan numbers: 0..4 wide, then the narrow plans, then the one-wave builds.
+// Plan numbers: 0..4 wide, then the narrow plans, then the one-wave builds,
+// then the lane-owned plan.
+int owned_plan_id() { return wide_plan_count() + narrow_plan_count() + 2; }
+int plan_for_raw(int plan) { return plan == owned_plan_id() ? wide_plan_count() + 1 : plan; }
 static bool narrow_plan(int plan) {
   return plan >= wide_plan_count() && plan < wide_plan_count() + narrow_plan_count();
 }
@@ -756,6 +759,11 @@ static int wide_entry(int plan) { return plan < wide_plan_count() ? plan : plan 
 
 void group_plan_shape(int plan, int* lanes, int* cpl) {
   if (narrow_plan(plan)) return narrow_plan_shape(plan - wide_plan_count(), lanes, cpl);
+  if (plan == owned_plan_id()) {  // 64 spots per wavefront of up to 16 x 16 pixels
+    *lanes = 1;
+    *cpl = 16;
+    return;
+  }
   plan = wide_entry(plan);
 #define SF_SHAPE(I, L, C, W) \
   if (plan == I) {           \
@@ -771,6 +779,7 @@ void group_plan_shape(int plan, int* lanes, int* cpl) {
 
 const void* group_kernel_symbol(int plan) {
   if (narrow_plan(plan)) return narrow_kernel_symbol(plan - wide_plan_count());
+  if (plan == owned_plan_id()) return owned_kernel_symbol();
   plan = wide_entry(plan);
 #define SF_SYM(I, L, C, W) \
   if (plan == I) return grp::sym_lw<L, C, W>();
@@ -781,6 +790,10 @@ const void* group_kernel_symbol(int plan) {
 
 hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t st) {
   if (narrow_plan(plan)) return launch_narrow_kernel(plan - wide_plan_count(), ka, grid, st);
+  if (plan == owned_plan_id()) {
+    if (ka.init_out) return hipErrorInvalidValue;  // start values in the launch: plan_for_raw
+    return launch_owned_kernel(ka, grid, st);
+  }
   plan = wide_entry(plan);
 #define SF_LAUNCH(I, L, C, W) \
   if (plan == I) return grp::launch_lw<L, C, W>(ka, grid, st);

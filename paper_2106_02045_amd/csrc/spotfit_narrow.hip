@@ -40,27 +40,14 @@
 #include "lanegroup.h"
 #include "spotfit_lm.h"
 #include "spotfit_start.h"
+#include "separable.h"
 
 namespace sf {
 namespace nrw {
 
 using namespace lm;
 using namespace lg;
-
-// Row factor of row r (held by in-group lane r % L as its own[r / L]) on every
-// lane of the group.
-template <int L, int CPL, int R>
-__device__ __forceinline__ double row_factor(const double (&own)[CPL]) {
-  return gbcast<L, R % L>(own[R / L]);
-}
-
-template <int L, int CPL, int HM, int R = 0, typename F>
-__device__ __forceinline__ void for_rows(const double (&own)[CPL], F&& f) {
-  if constexpr (R < HM) {
-    f(R, row_factor<L, CPL, R>(own));
-    for_rows<L, CPL, HM, R + 1>(own, f);
-  }
-}
+using namespace sep;
 
 // Zeros that the loads of a column outside a spot read instead (one row offset
 // of a 32 x 32 spot at most, as float or as 16-bit values).  Never written.  Not
@@ -93,23 +80,6 @@ struct NState {
   double Sx, Sxx, Sy, Syy, FG, D, Bx, Bsx, By, Bsy;
 };
 
-// Bound on the gap between chi^2 from the closed form and chi^2 summed over
-// the pixels, in units of 2^-53 ((w + h) / 2 chi^2 + (2|a| (N FG + F G) +
-// a^2 (N FF + F^2)) / N): the first-order rounding of the closed form's terms
-// (the cancellations in N FG - F G and in D) plus the direct sum's own
-// (sqrt(N) <= (w + h) / 2).  The largest gap measured over every workload,
-// in double precision on the host, was 26 units.
-constexpr double kChiGapUnits = 256.0;
-
-// Pixel value of a stored 32-bit pattern: a 16-bit count, or a float.
-template <int DT>
-__device__ __forceinline__ double pixel(uint32_t v) {
-  if constexpr (DT == SPOTFIT_U16)
-    return double(v);
-  else
-    return double(__uint_as_float(v));
-}
-
 // Start values of one spot (ini::moment_init_spot), out of line: its registers
 // are then not allocated across the fit's loop, which only saves what it keeps
 // live around this call.
@@ -117,14 +87,6 @@ template <int L, int CPL, int DT>
 __device__ __noinline__ void start_values_of(const void* data, spotfit_shape_t sh, int64_t off,
                                              int li, float* o4) {
   ini::moment_init_spot<L, CPL>(data, DT, sh, off, li, o4);
-}
-
-// Orders this wavefront's LDS writes before its later LDS reads (a workgroup
-// is one wavefront).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 // Fit every spot the source hands to this wavefront's groups.

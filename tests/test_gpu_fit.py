@@ -169,9 +169,11 @@ def test_run_to_run_bitwise(gpu):
 
 # Every compiled lane mapping of the separable kernel, selected through the
 # plan override (wide plans 0-4: lanes x columns 8x1, 8x2, 16x1, 16x2, 32x1;
-# narrow plans 5-8: 4x2, 4x4, 8x2, 16x2), reproduces the oracle's decisions.
-PLANS_UP_TO_8 = [0, 5]
-PLANS_UP_TO_16 = [1, 2, 3, 6, 7, 8, 9]
+# narrow plans 5-8: 4x2, 4x4, 8x2, 16x2; one-wave builds 9, 10; the lane-owned
+# plan 11: 4-lane groups of 4 spots, one per lane), reproduces the oracle's decisions.
+OWNED_PLAN = 11
+PLANS_UP_TO_8 = [0, 5, OWNED_PLAN]
+PLANS_UP_TO_16 = [1, 2, 3, 6, 7, 8, 9, OWNED_PLAN]
 PLANS_UP_TO_32 = [4, 8, 10]
 
 
@@ -209,6 +211,35 @@ def test_every_plan_matches_oracle(gpu, cls, plan, side):
     r = oracle.fit_batch(b, oracle.default_opts(), threads=8)
     c = _check_strict(f"plan {plan} (class {cls})", g, r)
     assert c["status_mismatch"] == 0
+
+
+def _troubled(b, f32):
+    """b with unusable spots (sigma 0, NaN start, unknown model) and, for float
+    data, a NaN pixel."""
+    sizes, init = b.sizes.copy(), b.init.copy()
+    data = b.data.astype(np.float32) if f32 else b.data.copy()
+    init[3, 2] = 0.0
+    init[7, 0] = np.nan
+    sizes[11, 2] = 7
+    if f32:
+        data[b.offsets[13] + 5] = np.nan
+    return spotgen.SpotBatch(data, sizes, b.offsets, init, b.truth, b.name)
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_lane_owned_plan_equals_narrow_bitwise(f32):
+    # The lane-owned mapping takes the narrow 4x4 kernel's arithmetic operation
+    # for operation: the same bits for every output, with close decisions re-taken
+    # by direct sums (float data: every chi^2), unusable spots and a ragged tail
+    # (a count that is not a multiple of the 64 spots of a wavefront).
+    b = _troubled(spotgen.workload("scale_15x15", n=20011), f32)
+    g_narrow = _plan_fit(b, 1, 6, 16)
+    g_owned = _plan_fit(b, 1, OWNED_PLAN, 16)
+    for k in g_narrow:
+        np.testing.assert_array_equal(g_owned[k], g_narrow[k], err_msg=k)
+    assert (g_owned["status"] == 5).sum() == 3  # BAD_INPUT
+    if f32:
+        assert g_owned["status"][13] == 4  # NOT_CONVERGED on the NaN pixel
 
 
 def test_bad_inputs_flagged(gpu):
