@@ -34,9 +34,10 @@ C_GRAD = {0: 66, 1: 88}
 C_TRIAL = 16
 
 
-# the narrow fit kernel's source and the headers its code comes from
-FIT_KERNEL_SOURCES = ("spotfit_narrow.hip", "spotfit_internal.h", "spotfit_lm.h", "lanegroup.h",
-                      "xlane.h", "spotfit_start.h")
+# the source of the fit kernel that the default workload runs (the lane-owned
+# kernel for spots up to 16 x 16) and the headers its code comes from
+FIT_KERNEL_SOURCES = ("spotfit_owned.hip", "spotfit_owned.h", "separable.h", "spotfit_internal.h",
+                      "spotfit_lm.h", "lanegroup.h", "xlane.h")
 
 
 def kernel_source_hash() -> str:

@@ -244,8 +244,9 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
     }
     c->occ_mixed[pl] = nb > 0 ? nb : 1;
   }
-  // default mixed-size plan: the narrow kernel's (4x2, 4x4, 16x2 lanes x columns)
-  c->mixed_plan = sf::mixed_plan_count() - sf::narrow_mixed_plan_count();
+  // default mixed-size plan: narrow 4x2 lanes x columns for <= 8 px, lane-owned
+  // (4 columns per lane) for <= 16 px, narrow 16x2 for <= 32 px (the last plan)
+  c->mixed_plan = sf::mixed_plan_count() - 1;
   if (const char* env = std::getenv("SPOTFIT_MIXED_PLAN")) {
     const int v = std::atoi(env);
     if (v >= 0 && v < sf::mixed_plan_count()) c->mixed_plan = v;
@@ -271,7 +272,7 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
   // lanes x 2 columns; <= 16: lane-owned (4-lane groups of 4 spots, 4 columns
   // per lane); <= 32: narrow, 16 lanes x 2 columns
   c->plan_for_class[0] = sf::wide_plan_count() + 0;
-  c->plan_for_class[1] = sf::owned_plan_id();
+  c->plan_for_class[1] = sf::owned_plan_id(4);
   c->plan_for_class[2] = sf::wide_plan_count() + 3;
   if (const char* env = std::getenv("SPOTFIT_GROUP_PLAN")) {
     // tuning override "a,b,c": plan for each size class

@@ -634,6 +634,30 @@ __device__ __forceinline__ void bucket_offsets(const int* cnt, int* cursor, int3
   for (int c = 0; c < 3; ++c) counters[c] = tot[c];
 }
 
+// Adds one to cnt[b] for every active lane with one LDS atomic per distinct
+// bucket of the wavefront (a ballot counts the lanes of a bucket); returns the
+// value cnt[b] had plus the lane's rank among the active lanes of its bucket.
+// Called by whole wavefronts.
+__device__ __forceinline__ int wave_bucket_add(int* cnt, int b, bool active) {
+  const int lane = __lane_id();
+  int res = 0;
+  uint64_t todo = __builtin_amdgcn_ballot_w64(active);
+  while (todo) {
+    const int leader = (int)__builtin_ctzll(todo);
+    const int bl = __builtin_amdgcn_readlane(b, leader);
+    const bool in = active && b == bl;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[bl], __builtin_popcountll(m));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if (in)
+      res = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    todo &= ~m;
+  }
+  return res;
+}
+
 __global__ void mixed_reset_kernel(MixedWs ws) {
   if (threadIdx.x < 8) ws.counters[threadIdx.x] = 0;
   if (threadIdx.x < kSortWords) ws.sort[threadIdx.x] = 0;
@@ -647,14 +671,21 @@ __global__ __launch_bounds__(1024) void mixed_small_classify_kernel(const spotfi
   if (threadIdx.x < 8) ws.counters[threadIdx.x] = 0;
   if (threadIdx.x < kSortBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
-  for (int64_t s = threadIdx.x; s < n; s += blockDim.x) atomicAdd(&cnt[side_bucket(sizes[s])], 1);
+  const int lane = __lane_id();
+  for (int64_t w0 = threadIdx.x & ~63; w0 < n; w0 += blockDim.x) {
+    const int64_t s = w0 + lane;
+    const bool act = s < n;
+    wave_bucket_add(cnt, act ? side_bucket(sizes[s]) : 0, act);
+  }
   __syncthreads();
   if (threadIdx.x == 0) bucket_offsets(cnt, cursor, ws.counters);
   __syncthreads();
-  for (int64_t s = threadIdx.x; s < n; s += blockDim.x) {
-    const int b = side_bucket(sizes[s]);
-    const int pos = atomicAdd(&cursor[b], 1);
-    ws.lists[(int64_t)bucket_class(b) * ws.cap + pos] = (int32_t)s;
+  for (int64_t w0 = threadIdx.x & ~63; w0 < n; w0 += blockDim.x) {
+    const int64_t s = w0 + lane;
+    const bool act = s < n;
+    const int b = act ? side_bucket(sizes[s]) : 0;
+    const int pos = wave_bucket_add(cursor, b, act);
+    if (act) ws.lists[(int64_t)bucket_class(b) * ws.cap + pos] = (int32_t)s;
   }
 }
 
@@ -664,8 +695,12 @@ __global__ __launch_bounds__(256) void mixed_count_kernel(const spotfit_shape_t*
   __shared__ int cnt[kSortBuckets];
   if (threadIdx.x < kSortBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < n) atomicAdd(&cnt[side_bucket(sizes[s])], 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); w0 < n; w0 += stride) {
+    const int64_t s = w0 + __lane_id();
+    const bool act = s < n;
+    wave_bucket_add(cnt, act ? side_bucket(sizes[s]) : 0, act);
+  }
   __syncthreads();
   if (threadIdx.x < kSortBuckets && cnt[threadIdx.x])
     atomicAdd(&ws.sort[threadIdx.x], cnt[threadIdx.x]);
@@ -676,21 +711,33 @@ __global__ void mixed_offsets_kernel(MixedWs ws) {
   if (threadIdx.x == 0) bucket_offsets(ws.sort, ws.sort + 64, ws.counters);
 }
 
-// Pass 3: each block reserves a range of every side's part of the list and
-// writes its spots there.
+// Pass 3: each block counts its spots per side again, reserves a range of every
+// side's part of the list and writes its spots there (same spots, same order).
 __global__ __launch_bounds__(256) void mixed_scatter_kernel(const spotfit_shape_t* sizes, int64_t n,
                                                            MixedWs ws) {
   __shared__ int cnt[kSortBuckets], base[kSortBuckets];
   if (threadIdx.x < kSortBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = s < n ? side_bucket(sizes[s]) : 0;
-  const int rank = s < n ? atomicAdd(&cnt[b], 1) : 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  for (int64_t w0 = first; w0 < n; w0 += stride) {
+    const int64_t s = w0 + __lane_id();
+    const bool act = s < n;
+    wave_bucket_add(cnt, act ? side_bucket(sizes[s]) : 0, act);
+  }
   __syncthreads();
-  if (threadIdx.x < kSortBuckets && cnt[threadIdx.x])
-    base[threadIdx.x] = atomicAdd(&ws.sort[64 + threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x < kSortBuckets) {
+    base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&ws.sort[64 + threadIdx.x], cnt[threadIdx.x]) : 0;
+    cnt[threadIdx.x] = 0;
+  }
   __syncthreads();
-  if (s < n) ws.lists[(int64_t)bucket_class(b) * ws.cap + base[b] + rank] = (int32_t)s;
+  for (int64_t w0 = first; w0 < n; w0 += stride) {
+    const int64_t s = w0 + __lane_id();
+    const bool act = s < n;
+    const int b = act ? side_bucket(sizes[s]) : 0;
+    const int rank = wave_bucket_add(cnt, b, act);
+    if (act) ws.lists[(int64_t)bucket_class(b) * ws.cap + base[b] + rank] = (int32_t)s;
+  }
 }
 
 template <int L0, int C0, int L1, int C1, int L2, int C2, int WPE, bool RAW>
@@ -746,12 +793,17 @@ static const void* sym_lw() {
 
 int wide_plan_count() { return 5; }
 
-int group_plan_count() { return wide_plan_count() + narrow_plan_count() + 3; }
+int group_plan_count() { return wide_plan_count() + narrow_plan_count() + 4; }
 
 // Plan numbers: 0..4 wide, then the narrow plans, then the one-wave builds,
-// then the lane-owned plan.
-int owned_plan_id() { return wide_plan_count() + narrow_plan_count() + 2; }
-int plan_for_raw(int plan) { return plan == owned_plan_id() ? wide_plan_count() + 1 : plan; }
+// then the lane-owned plans (4 spots per group, then 2).
+int owned_plan_id(int spots_per_group) {
+  return wide_plan_count() + narrow_plan_count() + (spots_per_group == 2 ? 3 : 2);
+}
+static int owned_of(int plan) {
+  return plan == owned_plan_id(4) ? 4 : plan == owned_plan_id(2) ? 2 : 0;
+}
+int plan_for_raw(int plan) { return owned_of(plan) ? wide_plan_count() + 1 : plan; }
 static bool narrow_plan(int plan) {
   return plan >= wide_plan_count() && plan < wide_plan_count() + narrow_plan_count();
 }
@@ -759,9 +811,9 @@ static int wide_entry(int plan) { return plan < wide_plan_count() ? plan : plan 
 
 void group_plan_shape(int plan, int* lanes, int* cpl) {
   if (narrow_plan(plan)) return narrow_plan_shape(plan - wide_plan_count(), lanes, cpl);
-  if (plan == owned_plan_id()) {  // 64 spots per wavefront of up to 16 x 16 pixels
-    *lanes = 1;
-    *cpl = 16;
+  if (const int own = owned_of(plan)) {  // 64 / lanes spots per wavefront, up to 16 x 16 pixels
+    *lanes = 4 / own;
+    *cpl = 4 * own;
     return;
   }
   plan = wide_entry(plan);
@@ -779,7 +831,7 @@ void group_plan_shape(int plan, int* lanes, int* cpl) {
 
 const void* group_kernel_symbol(int plan) {
   if (narrow_plan(plan)) return narrow_kernel_symbol(plan - wide_plan_count());
-  if (plan == owned_plan_id()) return owned_kernel_symbol();
+  if (const int own = owned_of(plan)) return owned_kernel_symbol(own);
   plan = wide_entry(plan);
 #define SF_SYM(I, L, C, W) \
   if (plan == I) return grp::sym_lw<L, C, W>();
@@ -790,9 +842,9 @@ const void* group_kernel_symbol(int plan) {
 
 hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t st) {
   if (narrow_plan(plan)) return launch_narrow_kernel(plan - wide_plan_count(), ka, grid, st);
-  if (plan == owned_plan_id()) {
+  if (const int own = owned_of(plan)) {
     if (ka.init_out) return hipErrorInvalidValue;  // start values in the launch: plan_for_raw
-    return launch_owned_kernel(ka, grid, st);
+    return launch_owned_kernel(own, ka, grid, st);
   }
   plan = wide_entry(plan);
 #define SF_LAUNCH(I, L, C, W) \
@@ -831,7 +883,8 @@ hipError_t launch_mixed(int plan, const KArgs& ka, const MixedWs& ws, int grid, 
     hipLaunchKernelGGL(grp::mixed_small_classify_kernel, dim3(1), dim3(1024), 0, st, ka.sizes, ka.n, ws);
     e = hipGetLastError();
   } else {
-    const int64_t cb = (ka.n + 255) / 256;
+    // at most 1024 blocks, each going over its share of the spots a wavefront at a time
+    const int64_t cb = (ka.n + 255) / 256 < 1024 ? (ka.n + 255) / 256 : 1024;
     hipLaunchKernelGGL(grp::mixed_reset_kernel, dim3(1), dim3(kSortWords), 0, st, ws);
     e = hipGetLastError();
     if (e == hipSuccess) {

@@ -101,13 +101,13 @@ int fit_preclassified(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
 // columns per lane and holds spots with w, h <= lanes * cpl.  Plans below
 // wide_plan_count() keep a group's state in LDS and share its scalar work over
 // the lanes; the narrow plans after them keep it in registers on every lane; two
-// one-wave builds of wide plans follow, then the lane-owned plan
-// (owned_plan_id(): 4-lane groups of 4 spots, one per lane; shape 1 x 16, for
-// the 64 spots a wavefront holds).  The lane-owned kernel reads its start
-// values: a fit that computes them in its launch runs the narrow 4 x 4 plan
-// (plan_for_raw).
+// one-wave builds of wide plans follow, then the lane-owned plans
+// (owned_plan_id(4): 4-lane groups of 4 spots, one per lane, shape 1 x 16 for
+// the 64 spots a wavefront holds; owned_plan_id(2): 2 spots per group, a lane
+// pair each, shape 2 x 8).  The lane-owned kernel reads its start values: a fit
+// that computes them in its launch runs the narrow 4 x 4 plan (plan_for_raw).
 int group_plan_count();
-int owned_plan_id();
+int owned_plan_id(int spots_per_group);
 int plan_for_raw(int plan);
 void group_plan_shape(int plan, int* lanes, int* cpl);
 const void* group_kernel_symbol(int plan);
@@ -123,8 +123,9 @@ int narrow_mixed_plan_count();
 const void* narrow_mixed_kernel_symbol(int plan);
 // the lane-owned kernel (spots up to 16 x 16 pixels): resets ka.queue, then
 // fits ka.n < 2^31 spots handed out through that counter; reads ka.init
-const void* owned_kernel_symbol();
-hipError_t launch_owned_kernel(const KArgs& ka, int grid, hipStream_t st);
+// own: spots per 4-lane group (4 or 2)
+const void* owned_kernel_symbol(int own);
+hipError_t launch_owned_kernel(int own, const KArgs& ka, int grid, hipStream_t st);
 // the fit launch of a mixed batch whose spots the classify pass has bucketed
 hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid,
                                    hipStream_t st);

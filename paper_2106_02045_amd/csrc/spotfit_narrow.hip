@@ -41,6 +41,7 @@
 #include "spotfit_lm.h"
 #include "spotfit_start.h"
 #include "separable.h"
+#include "spotfit_owned.h"
 
 namespace sf {
 namespace nrw {
@@ -752,6 +753,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   }
 }
 
+// A mixed-size launch whose <= 16 px class runs the lane-owned mapping (4-lane
+// groups of 4 spots, CPL1 columns per lane); a launch that computes its start
+// values runs the narrow 4 x CPL1 mapping for that class instead.  The classes
+// run one after another, so their LDS state shares one region.
+template <int L0, int C0, int CPL1, int L2, int C2, int WPE, int DT, bool RAW>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_owned_mixed_kernel(
+    KArgs ka, MixedWs ws) {
+  static_assert(L0 <= 4 && 4 <= L2, "classes in order of size");
+  struct Narrow {
+    NState sts[64 / L0];
+    float4 cinit[RAW ? 2 * (64 / L0) : 1];
+  };
+  __shared__ union Lds {
+    Narrow n;
+    own::OShared o;
+  } lds;
+  const int start = blockIdx.x % 3;
+  for (int q = 0; q < 3; ++q) {
+    const int c = (start + q) % 3;
+    const int32_t* list = ws.lists + (int64_t)c * ws.cap;
+    int32_t* take = ws.counters + 3 + c;
+    const int32_t count = ws.counters[c];
+    if (c == 0) {
+      fit_narrow<L0, C0, DT, RAW>(ka, SpotQueue{list, take, count}, lds.n.sts, lds.n.cinit);
+    } else if (c == 1) {
+      if constexpr (RAW)
+        fit_narrow<4, CPL1, DT, RAW>(ka, SpotQueue{list, take, count}, lds.n.sts, lds.n.cinit);
+      else
+        own::fit_owned<CPL1, DT>(ka, list, take, count, lds.o);
+    } else {
+      fit_narrow<L2, C2, DT, RAW>(ka, SpotQueue{list, take, count}, lds.n.sts, lds.n.cinit);
+    }
+  }
+}
+
 }  // namespace nrw
 
 // The compiled narrow plans: (lanes per spot, columns per lane, min waves per SIMD).
@@ -790,9 +826,19 @@ const void* narrow_kernel_symbol(int plan) {
   X(0, 4, 2, 4, 4, 16, 2, 2)       \
   X(1, 4, 2, 8, 2, 16, 2, 2)
 
-int narrow_mixed_plan_count() { return 2; }
+// Mixed-size plans whose <= 16 px class is lane-owned: lanes and columns of
+// class 0, columns per lane of class 1, lanes and columns of class 2, min waves
+// per SIMD.
+#define SF_OWNED_MIXED_PLANS(X) X(2, 4, 2, 4, 16, 2, 2)
+
+int narrow_mixed_plan_count() { return 3; }
 
 const void* narrow_mixed_kernel_symbol(int plan) {
+#define SF_OMSYM(I, A, B, C, D, E, W) \
+  if (plan == I)                      \
+    return reinterpret_cast<const void*>(&nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_U16, false>);
+  SF_OWNED_MIXED_PLANS(SF_OMSYM)
+#undef SF_OMSYM
 #define SF_NMSYM(I, A, B, C, D, E, F, W) \
   if (plan == I)                         \
     return reinterpret_cast<const void*>(&nrw::fit_narrow_mixed_kernel<A, B, C, D, E, F, W, SPOTFIT_U16, false>);
@@ -822,6 +868,24 @@ hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws,
   }
   SF_NARROW_MIXED_PLANS(SF_NMLAUNCH)
 #undef SF_NMLAUNCH
+#define SF_OMLAUNCH(I, A, B, C, D, E, W)                                                         \
+  if (plan == I) {                                                                               \
+    if (ka.dtype == SPOTFIT_U16 && raw)                                                          \
+      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_U16, true>), dim3(grid), \
+                         dim3(64), 0, st, ka, ws);                                               \
+    else if (ka.dtype == SPOTFIT_U16)                                                            \
+      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_U16, false>), dim3(grid), \
+                         dim3(64), 0, st, ka, ws);                                               \
+    else if (raw)                                                                                \
+      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_F32, true>), dim3(grid), \
+                         dim3(64), 0, st, ka, ws);                                               \
+    else                                                                                         \
+      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_F32, false>), dim3(grid), \
+                         dim3(64), 0, st, ka, ws);                                               \
+    return hipGetLastError();                                                                    \
+  }
+  SF_OWNED_MIXED_PLANS(SF_OMLAUNCH)
+#undef SF_OMLAUNCH
   return hipErrorInvalidValue;
 }
 

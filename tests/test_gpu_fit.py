@@ -170,10 +170,11 @@ def test_run_to_run_bitwise(gpu):
 # Every compiled lane mapping of the separable kernel, selected through the
 # plan override (wide plans 0-4: lanes x columns 8x1, 8x2, 16x1, 16x2, 32x1;
 # narrow plans 5-8: 4x2, 4x4, 8x2, 16x2; one-wave builds 9, 10; the lane-owned
-# plan 11: 4-lane groups of 4 spots, one per lane), reproduces the oracle's decisions.
-OWNED_PLAN = 11
-PLANS_UP_TO_8 = [0, 5, OWNED_PLAN]
-PLANS_UP_TO_16 = [1, 2, 3, 6, 7, 8, 9, OWNED_PLAN]
+# plans 11 and 12: 4-lane groups of 4 spots, one per lane, or of 2 spots, a lane
+# pair each), reproduces the oracle's decisions.
+OWNED_PLANS = [11, 12]
+PLANS_UP_TO_8 = [0, 5] + OWNED_PLANS
+PLANS_UP_TO_16 = [1, 2, 3, 6, 7, 8, 9] + OWNED_PLANS
 PLANS_UP_TO_32 = [4, 8, 10]
 
 
@@ -226,20 +227,60 @@ def _troubled(b, f32):
     return spotgen.SpotBatch(data, sizes, b.offsets, init, b.truth, b.name)
 
 
+@pytest.mark.parametrize("plan", OWNED_PLANS)
 @pytest.mark.parametrize("f32", [False, True])
-def test_lane_owned_plan_equals_narrow_bitwise(f32):
+def test_lane_owned_plan_equals_narrow_bitwise(f32, plan):
     # The lane-owned mapping takes the narrow 4x4 kernel's arithmetic operation
     # for operation: the same bits for every output, with close decisions re-taken
     # by direct sums (float data: every chi^2), unusable spots and a ragged tail
     # (a count that is not a multiple of the 64 spots of a wavefront).
     b = _troubled(spotgen.workload("scale_15x15", n=20011), f32)
     g_narrow = _plan_fit(b, 1, 6, 16)
-    g_owned = _plan_fit(b, 1, OWNED_PLAN, 16)
+    g_owned = _plan_fit(b, 1, plan, 16)
     for k in g_narrow:
         np.testing.assert_array_equal(g_owned[k], g_narrow[k], err_msg=k)
     assert (g_owned["status"] == 5).sum() == 3  # BAD_INPUT
     if f32:
         assert g_owned["status"][13] == 4  # NOT_CONVERGED on the NaN pixel
+
+
+# mixed-size plans: 4 = narrow classes (4x2, 4x4, 16x2); 6 = the same with the
+# lane-owned mapping for the <= 16 px class
+NARROW_MIXED_PLAN, OWNED_MIXED_PLAN = 4, 6
+
+
+@pytest.mark.parametrize("raw", [False, True])
+def test_lane_owned_mixed_plan_equals_narrow_mixed_bitwise(raw):
+    # one persistent launch over spots of 7..32 px: the lane-owned class gives the
+    # narrow class's bits (a launch computing its start values keeps the narrow
+    # mapping for that class)
+    import os
+
+    import torch
+
+    import paper_2106_02045_amd as sf
+    b = spotgen.workload("mixed_7to32", n=30011)
+    dev = torch.device("cuda:0")
+    up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    outs = []
+    for plan in (NARROW_MIXED_PLAN, OWNED_MIXED_PLAN):
+        os.environ["SPOTFIT_MIXED_PLAN"] = str(plan)
+        try:
+            ctx = sf.Context(0)
+        finally:
+            del os.environ["SPOTFIT_MIXED_PLAN"]
+        ctx.reserve(b.n)
+        o = sf.default_options(max_side=32, schedule=sf.SCHEDULE_MIXED)
+        if raw:
+            out = ctx.fit_raw(up(b.data), up(b.sizes), up(b.offsets), o, want_evals=True)
+        else:
+            out = ctx.fit_spots(up(b.data), up(b.sizes), up(b.offsets), up(b.init), o,
+                                want_evals=True)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in out.items()})
+        ctx.close()
+    for k in outs[0]:
+        np.testing.assert_array_equal(outs[1][k], outs[0][k], err_msg=k)
 
 
 def test_bad_inputs_flagged(gpu):
