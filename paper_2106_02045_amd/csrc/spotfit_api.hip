@@ -25,9 +25,11 @@ struct spotfit_ctx {
   // separable kernel: plan used for each size class (max side <= 8, <= 16, <= 32)
   // and resident 64-lane workgroups per CU of every plan
   int plan_for_class[3];
+  bool plan_forced[3];  // set by the SPOTFIT_GROUP_PLAN override: no switch by batch size
   int occ_plan[16];
   // mixed-size batches: plan and residency of the persistent kernel, workspace
   int mixed_plan;
+  bool mixed_forced;  // set by the SPOTFIT_MIXED_PLAN override
   int occ_mixed[8];
   int32_t* ws;      // counters[8] then 3 lists of ws_cap spot indices
   int64_t ws_cap;
@@ -249,7 +251,10 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
   c->mixed_plan = sf::mixed_plan_count() - 1;
   if (const char* env = std::getenv("SPOTFIT_MIXED_PLAN")) {
     const int v = std::atoi(env);
-    if (v >= 0 && v < sf::mixed_plan_count()) c->mixed_plan = v;
+    if (v >= 0 && v < sf::mixed_plan_count()) {
+      c->mixed_plan = v;
+      c->mixed_forced = true;
+    }
   }
   c->ws = nullptr;
   c->ws_cap = 0;
@@ -268,11 +273,11 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
     delete c;
     return fail_hip(e, "hipMalloc (context buffers)");
   }
-  // default plan per size class (measured on MI355X): <= 8 px side: narrow, 4
-  // lanes x 2 columns; <= 16: lane-owned (4-lane groups of 4 spots, 4 columns
-  // per lane); <= 32: narrow, 16 lanes x 2 columns
-  c->plan_for_class[0] = sf::wide_plan_count() + 0;
-  c->plan_for_class[1] = sf::owned_plan_id(4);
+  // default plan per size class (measured on MI355X): <= 8 px side: lane-owned
+  // (4-lane groups of 4 spots, 2 columns per lane); <= 16: lane-owned, 4 columns
+  // per lane; <= 32: narrow, 16 lanes x 2 columns
+  c->plan_for_class[0] = sf::owned_plan_id(2, 4);
+  c->plan_for_class[1] = sf::owned_plan_id(4, 4);
   c->plan_for_class[2] = sf::wide_plan_count() + 3;
   if (const char* env = std::getenv("SPOTFIT_GROUP_PLAN")) {
     // tuning override "a,b,c": plan for each size class
@@ -283,7 +288,10 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
       for (int i = 0; i < 3; ++i) {
         int L = 0, C = 0;
         sf::group_plan_shape(want[i], &L, &C);
-        if (L * C >= side[i]) c->plan_for_class[i] = want[i];
+        if (L * C >= side[i]) {
+          c->plan_for_class[i] = want[i];
+          c->plan_forced[i] = true;
+        }
       }
     }
   }
@@ -367,6 +375,11 @@ int check_call(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
 // of the wide mixed-size plan (measured: faster up to 40,000 spots of the
 // serving and mixed workloads, slower from 400,000).
 constexpr int64_t kLeanMaxSpots = 65536;
+// The lane-owned plans hold 64 (or 32) spots per wavefront and make a pass per
+// spot of a group each step: they pay off when every resident lane fits several
+// spots in turn (measured on 15x15 and 7x7 spots: slower up to 262k spots,
+// 19-26 % faster at 1M); a smaller batch takes the narrow plan of the same bits.
+constexpr int64_t kOwnedMinSpotsPerLane = 4;
 
 // Enqueue one fit with validated options o and n > 0.  init_out not NULL (with
 // init NULL): the separable double-precision kernels compute the start values
@@ -423,8 +436,11 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
     // latency: the wide mixed-size plan (8, 16, 32 lanes per spot); up to
     // kLeanMaxSpots spots its one-wave-per-SIMD build, which spills no
     // registers (those batches leave most of the chip idle anyway)
-    const int mplan = o.plan_hint == SPOTFIT_PLAN_LATENCY ? (n <= kLeanMaxSpots ? 3 : 0)
-                                                          : ctx->mixed_plan;
+    int mplan = o.plan_hint == SPOTFIT_PLAN_LATENCY ? (n <= kLeanMaxSpots ? 3 : 0)
+                                                    : ctx->mixed_plan;
+    if (sf::mixed_plan_narrow(mplan) != mplan && !ctx->mixed_forced &&
+        n < kOwnedMinSpotsPerLane * (int64_t)ctx->n_cu * ctx->occ_mixed[mplan] * 64)
+      mplan = sf::mixed_plan_narrow(mplan);
     const int64_t resident = (int64_t)ctx->n_cu * ctx->occ_mixed[mplan];
     const int64_t need = (n + 1) / 2;
     const int grid = (int)(need < resident ? need : resident);
@@ -439,7 +455,13 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
     const int one_wave = sf::wide_plan_count() + sf::narrow_plan_count();
     const int wide_for_class[3] = {0, 2, 4}, lean_for_class[3] = {0, one_wave, one_wave + 1};
     int plan = ctx->plan_for_class[cls];
-    if (init_out) plan = sf::plan_for_raw(plan);
+    if (sf::plan_for_raw(plan) != plan) {  // a lane-owned plan
+      int ol = 0, oc = 0;
+      sf::group_plan_shape(plan, &ol, &oc);
+      const int64_t lanes_resident = (int64_t)ctx->n_cu * ctx->occ_plan[plan] * (64 / ol);
+      if (init_out || (!ctx->plan_forced[cls] && n < kOwnedMinSpotsPerLane * lanes_resident))
+        plan = sf::plan_for_raw(plan);
+    }
     int lanes = 0, cpl = 0;
     if (o.plan_hint == SPOTFIT_PLAN_LATENCY) {
       plan = wide_for_class[cls];

@@ -102,12 +102,12 @@ int fit_preclassified(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
 // wide_plan_count() keep a group's state in LDS and share its scalar work over
 // the lanes; the narrow plans after them keep it in registers on every lane; two
 // one-wave builds of wide plans follow, then the lane-owned plans
-// (owned_plan_id(4): 4-lane groups of 4 spots, one per lane, shape 1 x 16 for
-// the 64 spots a wavefront holds; owned_plan_id(2): 2 spots per group, a lane
-// pair each, shape 2 x 8).  The lane-owned kernel reads its start values: a fit
-// that computes them in its launch runs the narrow 4 x 4 plan (plan_for_raw).
+// (owned_plan_id(cpl, own): 4-lane groups of `own` spots with `cpl` columns per
+// lane; shape (4 / own) x (cpl * own), so that 64 / lanes is the spots a
+// wavefront holds).  The lane-owned kernel reads its start values: a fit that
+// computes them in its launch runs the narrow 4 x cpl plan (plan_for_raw).
 int group_plan_count();
-int owned_plan_id(int spots_per_group);
+int owned_plan_id(int cpl, int own);
 int plan_for_raw(int plan);
 void group_plan_shape(int plan, int* lanes, int* cpl);
 const void* group_kernel_symbol(int plan);
@@ -123,9 +123,13 @@ int narrow_mixed_plan_count();
 const void* narrow_mixed_kernel_symbol(int plan);
 // the lane-owned kernel (spots up to 16 x 16 pixels): resets ka.queue, then
 // fits ka.n < 2^31 spots handed out through that counter; reads ka.init
-// own: spots per 4-lane group (4 or 2)
-const void* owned_kernel_symbol(int own);
-hipError_t launch_owned_kernel(int own, const KArgs& ka, int grid, hipStream_t st);
+// cpl: columns per lane (4: spots up to 16 px, 2: up to 8 px); own: spots per
+// 4-lane group (4 or 2); the built pairs are (4, 4), (4, 2) and (2, 4)
+const void* owned_kernel_symbol(int cpl, int own);
+hipError_t launch_owned_kernel(int cpl, int own, const KArgs& ka, int grid, hipStream_t st);
+// the mixed-size plan that gives `plan`'s bits with narrow mappings only (the
+// lane-owned plan's all-narrow twin), or `plan` itself
+int mixed_plan_narrow(int plan);
 // the fit launch of a mixed batch whose spots the classify pass has bucketed
 hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws, int grid,
                                    hipStream_t st);

@@ -415,8 +415,8 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
           S.By = __builtin_fma(-y, FG, R1);                       // sum (r - y) e s(r)
           S.Bsy = __builtin_fma(-y, __builtin_fma(2.0, R1, -y * FG), R2);  // sum (r - y)^2 e s(r)
         }
-        const double F = Sx * Sy, FF = Sxx * Syy;
-        const double D = Nn * FF - F * F;
+        const Amplitudes am = amplitudes(Nn, Sx, Sxx, Sy, Syy, FG, Gs);
+        const double D = am.D;
         S.Sx = Sx;
         S.Sxx = Sxx;
         S.Sy = Sy;
@@ -424,23 +424,13 @@ __device__ __forceinline__ void fit_narrow(const KArgs& ka, const SpotQueue& q, 
         S.FG = FG;
         S.D = D;
         const bool okD = D > 0.0 && __builtin_isfinite(D);
-        const double iD = rcp_nr(D);
-        a = (Nn * FG - F * Gs) * iD;
-        b = (Gs * FF - F * FG) * iD;
+        a = am.a;
+        b = am.b;
         // direct sum over the pixels: always for float data; for 16-bit data
         // only where a close decision is being re-taken
         bool direct = DT != SPOTFIT_U16;
         if constexpr (DT == SPOTFIT_U16) {
-          // Eq. 2 at the amplitudes of Eq. 6: with sum r = sum f r = 0 (Eq. 4),
-          // chi^2 = sum (g - mean g)^2 - a^2 sum (f - mean f)^2 = (V - a^2 D) / N,
-          // V = N sum g^2 - G^2 exact for 16-bit data; no second pixel pass.
-          // Bright spots cancel the most: up to 3e-11 of chi^2 measured.
-          const double iNn = rcp_nr(Nn);
-          const double c2 = (Vs - a * a * D) * iNn;
-          chi = c2 > 0.0 ? c2 : 0.0;
-          chi_err = kChiGapUnits * 0x1p-53 *
-                    (0.5 * double(w + h) * chi +
-                     (2.0 * fabs(a) * (Nn * FG + F * Gs) + a * a * (Nn * FF + F * F)) * iNn);
+          chi_closed(Vs, am, Nn, FG, Gs, w, h, chi, chi_err);  // Eq. 2, no second pixel pass
           direct = mode == kRecheckBest || mode == kRecheckCand;
         }
         if (__builtin_amdgcn_ballot_w64(direct) != 0 && direct) {

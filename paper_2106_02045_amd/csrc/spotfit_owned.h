@@ -432,11 +432,8 @@ __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, 
       if (any_dr) {
         // the residual sum of squares at the amplitudes of Eq. 6, r = alpha f + beta - g
         // (every group runs the loop for its loads; the spots that asked sum)
-        const double F = Sx * Sy, FF = Sxx * Syy;
-        const double D = Nn * FF - F * F;
-        const double iD = rcp_nr(D);
-        const double ap = (Nn * FG - F * Gp) * iD;
-        const double bp = (Gp * FF - F * FG) * iD;
+        const Amplitudes amp = amplitudes(Nn, Sx, Sxx, Sy, Syy, FG, Gp);
+        const double ap = amp.a, bp = amp.b;
         double aex[CPL], bm[CPL], c2[CPL];
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
@@ -496,21 +493,12 @@ __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, 
         Bsy = __builtin_fma(-y, __builtin_fma(2.0, R1, -y * FG), R2);  // sum (r - y)^2 e s(r)
       }
       const double Nn = double(w * h);
-      const double F = Sx * Sy, FF = Sxx * Syy;
-      D = Nn * FF - F * F;
+      const Amplitudes am = amplitudes(Nn, Sx, Sxx, Sy, Syy, FG, Gs);
+      D = am.D;
       const bool okD = D > 0.0 && __builtin_isfinite(D);
-      const double iD = rcp_nr(D);
-      a = (Nn * FG - F * Gs) * iD;
-      b = (Gs * FF - F * FG) * iD;
-      if constexpr (DT == SPOTFIT_U16) {
-        // Eq. 2 at the amplitudes of Eq. 6: chi^2 = (V - a^2 D) / N (sum r = sum f r = 0, Eq. 4)
-        const double iNn = rcp_nr(Nn);
-        const double c2 = (Vs - a * a * D) * iNn;
-        chi = c2 > 0.0 ? c2 : 0.0;
-        chi_err = kChiGapUnits * 0x1p-53 *
-                  (0.5 * double(w + h) * chi +
-                   (2.0 * fabs(a) * (Nn * FG + F * Gs) + a * a * (Nn * FF + F * F)) * iNn);
-      }
+      a = am.a;
+      b = am.b;
+      if constexpr (DT == SPOTFIT_U16) chi_closed(Vs, am, Nn, FG, Gs, w, h, chi, chi_err);  // Eq. 2
       if (dir_own) {
         chi = S.sum[kChiDirect][lane];
         chi_err = 0.0;

@@ -22,36 +22,39 @@ __global__ void owned_queue_reset_kernel(int32_t* take) {
 
 }  // namespace own
 
-// The lane-owned plans: 4-lane groups of 4 columns per lane (spots up to 16 x
-// 16 pixels) at 2 waves per SIMD, holding 4 spots per group (one per lane, 64
+// The lane-owned plans, at 2 waves per SIMD: 4-lane groups with 4 columns per
+// lane (spots up to 16 x 16 pixels) holding 4 spots per group (one per lane, 64
 // per wavefront) or 2 (a lane pair per spot, 32 per wavefront: half the pixels
-// in flight, twice the scalar work per spot).
-constexpr int kOwnedCpl = 4, kOwnedWpe = 2;
+// in flight, twice the scalar work per spot); 2 columns per lane (spots up to
+// 8 x 8), 4 spots per group.
+constexpr int kOwnedWpe = 2;
 
-const void* owned_kernel_symbol(int own) {
-  return own == 2 ? reinterpret_cast<const void*>(&own::fit_owned_kernel<kOwnedCpl, kOwnedWpe, SPOTFIT_U16, 2>)
-                  : reinterpret_cast<const void*>(&own::fit_owned_kernel<kOwnedCpl, kOwnedWpe, SPOTFIT_U16, 4>);
+#define SF_OWNED_KERNELS(X) X(4, 4) X(4, 2) X(2, 4)
+
+const void* owned_kernel_symbol(int cpl, int own) {
+#define SF_OSYM(C, O) \
+  if (cpl == C && own == O) return reinterpret_cast<const void*>(&own::fit_owned_kernel<C, kOwnedWpe, SPOTFIT_U16, O>);
+  SF_OWNED_KERNELS(SF_OSYM)
+#undef SF_OSYM
+  return nullptr;
 }
 
-template <int OWN>
-static void launch_owned(const KArgs& ka, int grid, hipStream_t st) {
-  if (ka.dtype == SPOTFIT_U16)
-    hipLaunchKernelGGL((own::fit_owned_kernel<kOwnedCpl, kOwnedWpe, SPOTFIT_U16, OWN>), dim3(grid), dim3(64),
-                       0, st, ka);
-  else
-    hipLaunchKernelGGL((own::fit_owned_kernel<kOwnedCpl, kOwnedWpe, SPOTFIT_F32, OWN>), dim3(grid), dim3(64),
-                       0, st, ka);
-}
-
-hipError_t launch_owned_kernel(int own, const KArgs& ka, int grid, hipStream_t st) {
-  if (own != 2 && own != 4) return hipErrorInvalidValue;
+hipError_t launch_owned_kernel(int cpl, int own, const KArgs& ka, int grid, hipStream_t st) {
+  if (!owned_kernel_symbol(cpl, own)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(own::owned_queue_reset_kernel, dim3(1), dim3(64), 0, st, ka.queue);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (own == 2)
-    launch_owned<2>(ka, grid, st);
-  else
-    launch_owned<4>(ka, grid, st);
+#define SF_OLAUNCH(C, O)                                                                          \
+  if (cpl == C && own == O) {                                                                     \
+    if (ka.dtype == SPOTFIT_U16)                                                                  \
+      hipLaunchKernelGGL((own::fit_owned_kernel<C, kOwnedWpe, SPOTFIT_U16, O>), dim3(grid), dim3(64), 0, \
+                         st, ka);                                                                 \
+    else                                                                                          \
+      hipLaunchKernelGGL((own::fit_owned_kernel<C, kOwnedWpe, SPOTFIT_F32, O>), dim3(grid), dim3(64), 0, \
+                         st, ka);                                                                 \
+  }
+  SF_OWNED_KERNELS(SF_OLAUNCH)
+#undef SF_OLAUNCH
   return hipGetLastError();
 }
 

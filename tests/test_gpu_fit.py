@@ -170,10 +170,12 @@ def test_run_to_run_bitwise(gpu):
 # Every compiled lane mapping of the separable kernel, selected through the
 # plan override (wide plans 0-4: lanes x columns 8x1, 8x2, 16x1, 16x2, 32x1;
 # narrow plans 5-8: 4x2, 4x4, 8x2, 16x2; one-wave builds 9, 10; the lane-owned
-# plans 11 and 12: 4-lane groups of 4 spots, one per lane, or of 2 spots, a lane
-# pair each), reproduces the oracle's decisions.
+# plans 11 and 12: 4-lane groups with 4 columns per lane holding 4 spots, one per
+# lane, or 2 spots, a lane pair each; 13: 2 columns per lane, 4 spots per group),
+# reproduces the oracle's decisions.
 OWNED_PLANS = [11, 12]
-PLANS_UP_TO_8 = [0, 5] + OWNED_PLANS
+OWNED_PLAN_8 = 13
+PLANS_UP_TO_8 = [0, 5] + OWNED_PLANS + [OWNED_PLAN_8]
 PLANS_UP_TO_16 = [1, 2, 3, 6, 7, 8, 9] + OWNED_PLANS
 PLANS_UP_TO_32 = [4, 8, 10]
 
@@ -242,6 +244,19 @@ def test_lane_owned_plan_equals_narrow_bitwise(f32, plan):
     assert (g_owned["status"] == 5).sum() == 3  # BAD_INPUT
     if f32:
         assert g_owned["status"][13] == 4  # NOT_CONVERGED on the NaN pixel
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_lane_owned_small_plan_equals_narrow_bitwise(f32):
+    # spots up to 8 px: the lane-owned plan with 2 columns per lane against the
+    # narrow 4x2 plan
+    m = spotgen.workload("mixed_7to32", n=60000)
+    b = _troubled(m.subset(np.nonzero(m.sizes[:, 0] <= 8)[0]), f32)
+    g_narrow = _plan_fit(b, 0, 5, 8)
+    g_owned = _plan_fit(b, 0, OWNED_PLAN_8, 8)
+    for k in g_narrow:
+        np.testing.assert_array_equal(g_owned[k], g_narrow[k], err_msg=k)
+    assert (g_owned["status"] == 5).sum() == 3
 
 
 # mixed-size plans: 4 = narrow classes (4x2, 4x4, 16x2); 6 = the same with the
