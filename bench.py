@@ -126,6 +126,11 @@ def parse():
                          "serving workload at --serve-fps (Poisson arrivals) through the "
                          "serving loop and report their latency (0: skip)")
     ap.add_argument("--serve-fps", type=float, default=1000.0)
+    ap.add_argument("--e2e-reps", type=int, default=5,
+                    help="after the timed steps, this many end-to-end calls: pinned host inputs to "
+                         "the device, the fit, results back to pinned host memory (0: skip)")
+    ap.add_argument("--cpu-sample-1t", type=int, default=30000,
+                    help="spots of the same workload fitted by the oracle on one thread")
     return ap.parse_args()
 
 
@@ -230,6 +235,35 @@ def main():
 
     achieved_tflops = flops / k_avg_s / 1e12
     hbm_gbps = alg_bytes / k_avg_s / 1e9
+    traffic = measured_traffic(a.workload, a.precision, a.schedule)
+
+    # end to end (outside the timed region): pinned host inputs -> device, the fit,
+    # the results -> pinned host memory, one synchronisation per call
+    e2e = None
+    if a.e2e_reps > 0 and not groups:
+        h_in = [torch.from_numpy(np.ascontiguousarray(x)).pin_memory()
+                for x in (batch.data, batch.sizes, batch.offsets, batch.init)]
+        d_in = [torch.empty_like(x, device=dev) for x in h_in]
+        h_out = {k: torch.empty(v.shape, dtype=v.dtype).pin_memory() for k, v in out.items()}
+
+        def e2e_call():
+            for h, d in zip(h_in, d_in):
+                d.copy_(h, non_blocking=True)
+            ctx.fit_spots(*d_in, opts, out=out, stream=stream)
+            for k, v in out.items():
+                h_out[k].copy_(v, non_blocking=True)
+            torch.cuda.synchronize()
+
+        e2e_call()
+        t0 = time.perf_counter()
+        for _ in range(a.e2e_reps):
+            e2e_call()
+        e_s = (time.perf_counter() - t0) / a.e2e_reps
+        in_bytes = sum(x.numel() * x.element_size() for x in h_in)
+        out_bytes = sum(v.numel() * v.element_size() for v in h_out.values())
+        e2e = {"fits_per_s": n / e_s, "ms_per_call": e_s * 1e3, "reps": a.e2e_reps,
+               "host_to_device_bytes": in_bytes, "device_to_host_bytes": out_bytes}
+        del h_in, d_in, h_out
 
     # serving: frames with Poisson arrivals through the serving loop (outside the
     # timed region; its own clock is per frame, arrival -> results on the host)
@@ -280,6 +314,14 @@ def main():
                "sample": f"first {m} spots of {a.workload} (same generator and seed), "
                          f"{cs:.2f} s wall on {threads} threads",
                "host": hc, "build": flags}
+        if a.cpu_sample_1t > 0:
+            m1 = min(a.cpu_sample_1t, n)
+            sub1 = sub.subset(np.arange(m1)) if m1 < m else sub
+            c0 = time.perf_counter()
+            oracle.fit_batch(sub1, oo, threads=1, library=lib)
+            c1 = time.perf_counter() - c0
+            cpu["single_thread"] = {"value": m1 / c1, "unit": "fits/s", "cores": 1,
+                                    "sample": f"first {m1} spots of {a.workload}, {c1:.2f} s wall"}
 
     parity = None
     if a.parity_sample > 0:
@@ -321,9 +363,11 @@ def main():
                    "launches_per_step": max(1, len(groups))},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_ALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_ALU_TFLOPS,
-                     "traffic": measured_traffic(a.workload, a.precision, a.schedule)},
+                     "traffic": traffic},
         "hbm": {"achieved_algorithmic_GBps": hbm_gbps, "peak_GBps": PEAK_HBM_GBPS,
-                "frac": hbm_gbps / PEAK_HBM_GBPS, "bytes_per_launch": alg_bytes},
+                "frac": hbm_gbps / PEAK_HBM_GBPS, "bytes_per_launch": alg_bytes,
+                "measured_GBps": traffic / k_avg_s / 1e9 if traffic is not None else None},
+        "end_to_end": e2e,
         "kernel_ms_avg": k_avg_s * 1e3,
         "exp_per_s": exps / k_avg_s,
         "evals_per_spot": {"grad": float(ng.mean()), "trial": float(nt.mean())},
