@@ -110,8 +110,11 @@ typedef enum {
 
 /* Which lane mapping the double-precision kernel uses. */
 typedef enum {
-  SPOTFIT_PLAN_THROUGHPUT = 0, /* default: few lanes per spot (4 up to 16x16), the most spots
-                                  per second for batches that fill the GPU              */
+  SPOTFIT_PLAN_THROUGHPUT = 0, /* default: the most spots per second for batches that fill
+                                  the GPU.  Spots up to 16x16 px: 4-lane groups that fit 4
+                                  spots at once, one per lane, when the batch gives every
+                                  resident lane at least 4 spots, else 4 lanes per spot (the
+                                  same bits); larger spots: 16 lanes per spot            */
   SPOTFIT_PLAN_LATENCY = 1     /* one lane per column (8, 16 or 32 lanes per spot): each
                                   evaluation step is shorter, so a batch too small to
                                   fill the GPU (a camera frame) finishes sooner; results
