@@ -246,8 +246,9 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
     }
     c->occ_mixed[pl] = nb > 0 ? nb : 1;
   }
-  // default mixed-size plan: narrow 4x2 lanes x columns for <= 8 px, lane-owned
-  // (4 columns per lane) for <= 16 px, narrow 16x2 for <= 32 px (the last plan)
+  // default mixed-size plan (the last): narrow 4x2 lanes x columns for <= 8 px,
+  // lane-owned 4-lane groups of 4 spots for <= 16 px, lane-owned 16-lane groups of
+  // 4 spots for <= 32 px
   c->mixed_plan = sf::mixed_plan_count() - 1;
   if (const char* env = std::getenv("SPOTFIT_MIXED_PLAN")) {
     const int v = std::atoi(env);
@@ -273,12 +274,13 @@ int spotfit_ctx_create(spotfit_ctx_t** out, int device) {
     delete c;
     return fail_hip(e, "hipMalloc (context buffers)");
   }
-  // default plan per size class (measured on MI355X): <= 8 px side: lane-owned
-  // (4-lane groups of 4 spots, 2 columns per lane); <= 16: lane-owned, 4 columns
-  // per lane; <= 32: narrow, 16 lanes x 2 columns
-  c->plan_for_class[0] = sf::owned_plan_id(2, 4);
-  c->plan_for_class[1] = sf::owned_plan_id(4, 4);
-  c->plan_for_class[2] = sf::wide_plan_count() + 3;
+  // default plan per size class (measured on MI355X), all lane-owned (taken for
+  // batches large enough, else the narrow plan of the same bits): <= 8 px side:
+  // 4-lane groups of 4 spots, 2 columns per lane; <= 16: 4 columns per lane;
+  // <= 32: 16-lane groups of 4 spots, 2 columns per lane
+  c->plan_for_class[0] = sf::owned_plan_id(4, 2, 4);
+  c->plan_for_class[1] = sf::owned_plan_id(4, 4, 4);
+  c->plan_for_class[2] = sf::owned_plan_id(16, 2, 4);
   if (const char* env = std::getenv("SPOTFIT_GROUP_PLAN")) {
     // tuning override "a,b,c": plan for each size class
     int a = -1, b = -1, d = -1;

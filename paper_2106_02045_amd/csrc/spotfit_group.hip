@@ -793,28 +793,30 @@ static const void* sym_lw() {
 
 int wide_plan_count() { return 5; }
 
-// The lane-owned plans: columns per lane, spots per group.
-static const int kOwned[3][2] = {{4, 4}, {4, 2}, {2, 4}};
+// The lane-owned plans: lanes per group, columns per lane, spots per group.
+constexpr int kOwnedPlans = 5;
+static const int kOwned[kOwnedPlans][3] = {{4, 4, 4}, {4, 4, 2}, {4, 2, 4}, {16, 2, 4}, {16, 2, 16}};
 
-int group_plan_count() { return wide_plan_count() + narrow_plan_count() + 2 + 3; }
+int group_plan_count() { return wide_plan_count() + narrow_plan_count() + 2 + kOwnedPlans; }
 
 // Plan numbers: 0..4 wide, then the narrow plans, then the one-wave builds,
 // then the lane-owned plans in kOwned's order.
 static int owned_base() { return wide_plan_count() + narrow_plan_count() + 2; }
-int owned_plan_id(int cpl, int own) {
-  for (int i = 0; i < 3; ++i)
-    if (kOwned[i][0] == cpl && kOwned[i][1] == own) return owned_base() + i;
+int owned_plan_id(int lanes, int cpl, int own) {
+  for (int i = 0; i < kOwnedPlans; ++i)
+    if (kOwned[i][0] == lanes && kOwned[i][1] == cpl && kOwned[i][2] == own) return owned_base() + i;
   return -1;
 }
 // index into kOwned, or -1
 static int owned_of(int plan) {
   const int i = plan - owned_base();
-  return i >= 0 && i < 3 ? i : -1;
+  return i >= 0 && i < kOwnedPlans ? i : -1;
 }
-// narrow 4x2 (plan 5) or 4x4 (plan 6) for the lane-owned plans of 2 or 4 columns per lane
+// the narrow plan of the same lanes x columns (4x2: plan 5, 4x4: 6, 16x2: 8)
 int plan_for_raw(int plan) {
   const int i = owned_of(plan);
-  return i < 0 ? plan : wide_plan_count() + (kOwned[i][0] == 2 ? 0 : 1);
+  if (i < 0) return plan;
+  return wide_plan_count() + (kOwned[i][0] == 16 ? 3 : kOwned[i][1] == 2 ? 0 : 1);
 }
 static bool narrow_plan(int plan) {
   return plan >= wide_plan_count() && plan < wide_plan_count() + narrow_plan_count();
@@ -824,8 +826,8 @@ static int wide_entry(int plan) { return plan < wide_plan_count() ? plan : plan 
 void group_plan_shape(int plan, int* lanes, int* cpl) {
   if (narrow_plan(plan)) return narrow_plan_shape(plan - wide_plan_count(), lanes, cpl);
   if (const int i = owned_of(plan); i >= 0) {  // 64 / lanes spots per wavefront
-    *lanes = 4 / kOwned[i][1];
-    *cpl = kOwned[i][0] * kOwned[i][1];
+    *lanes = kOwned[i][0] / kOwned[i][2];
+    *cpl = kOwned[i][1] * kOwned[i][2];
     return;
   }
   plan = wide_entry(plan);
@@ -843,7 +845,7 @@ void group_plan_shape(int plan, int* lanes, int* cpl) {
 
 const void* group_kernel_symbol(int plan) {
   if (narrow_plan(plan)) return narrow_kernel_symbol(plan - wide_plan_count());
-  if (const int i = owned_of(plan); i >= 0) return owned_kernel_symbol(kOwned[i][0], kOwned[i][1]);
+  if (const int i = owned_of(plan); i >= 0) return owned_kernel_symbol(kOwned[i][0], kOwned[i][1], kOwned[i][2]);
   plan = wide_entry(plan);
 #define SF_SYM(I, L, C, W) \
   if (plan == I) return grp::sym_lw<L, C, W>();
@@ -856,7 +858,7 @@ hipError_t launch_group_kernel(int plan, const KArgs& ka, int grid, hipStream_t 
   if (narrow_plan(plan)) return launch_narrow_kernel(plan - wide_plan_count(), ka, grid, st);
   if (const int i = owned_of(plan); i >= 0) {
     if (ka.init_out) return hipErrorInvalidValue;  // start values in the launch: plan_for_raw
-    return launch_owned_kernel(kOwned[i][0], kOwned[i][1], ka, grid, st);
+    return launch_owned_kernel(kOwned[i][0], kOwned[i][1], kOwned[i][2], ka, grid, st);
   }
   plan = wide_entry(plan);
 #define SF_LAUNCH(I, L, C, W) \
@@ -879,9 +881,10 @@ int wide_mixed_plan_count() { return 4; }
 
 int mixed_plan_count() { return wide_mixed_plan_count() + narrow_mixed_plan_count(); }
 
-// narrow mixed plan 2 (lane-owned middle class) -> narrow mixed plan 0
+// narrow mixed plans 2 and 3 (lane-owned classes) -> narrow mixed plan 0
 int mixed_plan_narrow(int plan) {
-  return plan == wide_mixed_plan_count() + 2 ? wide_mixed_plan_count() : plan;
+  const int i = plan - wide_mixed_plan_count();
+  return i == 2 || i == 3 ? wide_mixed_plan_count() : plan;
 }
 
 const void* mixed_kernel_symbol(int plan) {

@@ -102,12 +102,13 @@ int fit_preclassified(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
 // wide_plan_count() keep a group's state in LDS and share its scalar work over
 // the lanes; the narrow plans after them keep it in registers on every lane; two
 // one-wave builds of wide plans follow, then the lane-owned plans
-// (owned_plan_id(cpl, own): 4-lane groups of `own` spots with `cpl` columns per
-// lane; shape (4 / own) x (cpl * own), so that 64 / lanes is the spots a
-// wavefront holds).  The lane-owned kernel reads its start values: a fit that
-// computes them in its launch runs the narrow 4 x cpl plan (plan_for_raw).
+// (owned_plan_id(lanes, cpl, own): groups of `lanes` lanes with `cpl` columns per
+// lane holding `own` spots; shape (lanes / own) x (cpl * own), so that 64 /
+// shape lanes is the spots a wavefront holds).  The lane-owned kernel reads its
+// start values: a fit that computes them in its launch runs the narrow
+// lanes x cpl plan (plan_for_raw).
 int group_plan_count();
-int owned_plan_id(int cpl, int own);
+int owned_plan_id(int lanes, int cpl, int own);
 int plan_for_raw(int plan);
 void group_plan_shape(int plan, int* lanes, int* cpl);
 const void* group_kernel_symbol(int plan);
@@ -123,10 +124,10 @@ int narrow_mixed_plan_count();
 const void* narrow_mixed_kernel_symbol(int plan);
 // the lane-owned kernel (spots up to 16 x 16 pixels): resets ka.queue, then
 // fits ka.n < 2^31 spots handed out through that counter; reads ka.init
-// cpl: columns per lane (4: spots up to 16 px, 2: up to 8 px); own: spots per
-// 4-lane group (4 or 2); the built pairs are (4, 4), (4, 2) and (2, 4)
-const void* owned_kernel_symbol(int cpl, int own);
-hipError_t launch_owned_kernel(int cpl, int own, const KArgs& ka, int grid, hipStream_t st);
+// lanes per group, columns per lane (spots up to lanes * cpl px), spots per
+// group; built: (4, 4, 4), (4, 4, 2), (4, 2, 4), (16, 2, 4), (16, 2, 16)
+const void* owned_kernel_symbol(int lanes, int cpl, int own);
+hipError_t launch_owned_kernel(int lanes, int cpl, int own, const KArgs& ka, int grid, hipStream_t st);
 // the mixed-size plan that gives `plan`'s bits with narrow mappings only (the
 // lane-owned plan's all-narrow twin), or `plan` itself
 int mixed_plan_narrow(int plan);

@@ -744,10 +744,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 }
 
 // A mixed-size launch whose <= 16 px class runs the lane-owned mapping (4-lane
-// groups of 4 spots, CPL1 columns per lane); a launch that computes its start
-// values runs the narrow 4 x CPL1 mapping for that class instead.  The classes
-// run one after another, so their LDS state shares one region.
-template <int L0, int C0, int CPL1, int L2, int C2, int WPE, int DT, bool RAW>
+// groups of 4 spots, CPL1 columns per lane), and with OWN2 > 0 its <= 32 px
+// class too (L2-lane groups of OWN2 spots); a launch that computes its start
+// values runs the narrow mappings of the same widths instead.  The classes run
+// one after another, so their LDS state shares one region.
+template <int L0, int C0, int CPL1, int L2, int C2, int OWN2, int WPE, int DT, bool RAW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void fit_owned_mixed_kernel(
     KArgs ka, MixedWs ws) {
   static_assert(L0 <= 4 && 4 <= L2, "classes in order of size");
@@ -771,9 +772,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
       if constexpr (RAW)
         fit_narrow<4, CPL1, DT, RAW>(ka, SpotQueue{list, take, count}, lds.n.sts, lds.n.cinit);
       else
-        own::fit_owned<CPL1, DT>(ka, list, take, count, lds.o);
+        own::fit_owned<4, CPL1, DT>(ka, list, take, count, lds.o);
     } else {
-      fit_narrow<L2, C2, DT, RAW>(ka, SpotQueue{list, take, count}, lds.n.sts, lds.n.cinit);
+      if constexpr (OWN2 > 0 && !RAW)
+        own::fit_owned<L2, C2, DT, OWN2>(ka, list, take, count, lds.o);
+      else
+        fit_narrow<L2, C2, DT, RAW>(ka, SpotQueue{list, take, count}, lds.n.sts, lds.n.cinit);
     }
   }
 }
@@ -817,16 +821,16 @@ const void* narrow_kernel_symbol(int plan) {
   X(1, 4, 2, 8, 2, 16, 2, 2)
 
 // Mixed-size plans whose <= 16 px class is lane-owned: lanes and columns of
-// class 0, columns per lane of class 1, lanes and columns of class 2, min waves
-// per SIMD.
-#define SF_OWNED_MIXED_PLANS(X) X(2, 4, 2, 4, 16, 2, 2)
+// class 0, columns per lane of class 1, lanes and columns of class 2, spots per
+// group of class 2 (0: narrow), min waves per SIMD.
+#define SF_OWNED_MIXED_PLANS(X) X(2, 4, 2, 4, 16, 2, 0, 2) X(3, 4, 2, 4, 16, 2, 4, 2)
 
-int narrow_mixed_plan_count() { return 3; }
+int narrow_mixed_plan_count() { return 4; }
 
 const void* narrow_mixed_kernel_symbol(int plan) {
-#define SF_OMSYM(I, A, B, C, D, E, W) \
-  if (plan == I)                      \
-    return reinterpret_cast<const void*>(&nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_U16, false>);
+#define SF_OMSYM(I, A, B, C, D, E, O, W) \
+  if (plan == I)                         \
+    return reinterpret_cast<const void*>(&nrw::fit_owned_mixed_kernel<A, B, C, D, E, O, W, SPOTFIT_U16, false>);
   SF_OWNED_MIXED_PLANS(SF_OMSYM)
 #undef SF_OMSYM
 #define SF_NMSYM(I, A, B, C, D, E, F, W) \
@@ -858,19 +862,19 @@ hipError_t launch_narrow_mixed_fit(int plan, const KArgs& ka, const MixedWs& ws,
   }
   SF_NARROW_MIXED_PLANS(SF_NMLAUNCH)
 #undef SF_NMLAUNCH
-#define SF_OMLAUNCH(I, A, B, C, D, E, W)                                                         \
+#define SF_OMLAUNCH(I, A, B, C, D, E, O, W)                                                      \
   if (plan == I) {                                                                               \
     if (ka.dtype == SPOTFIT_U16 && raw)                                                          \
-      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_U16, true>), dim3(grid), \
+      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, O, W, SPOTFIT_U16, true>), dim3(grid), \
                          dim3(64), 0, st, ka, ws);                                               \
     else if (ka.dtype == SPOTFIT_U16)                                                            \
-      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_U16, false>), dim3(grid), \
+      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, O, W, SPOTFIT_U16, false>), dim3(grid), \
                          dim3(64), 0, st, ka, ws);                                               \
     else if (raw)                                                                                \
-      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_F32, true>), dim3(grid), \
+      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, O, W, SPOTFIT_F32, true>), dim3(grid), \
                          dim3(64), 0, st, ka, ws);                                               \
     else                                                                                         \
-      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, W, SPOTFIT_F32, false>), dim3(grid), \
+      hipLaunchKernelGGL((nrw::fit_owned_mixed_kernel<A, B, C, D, E, O, W, SPOTFIT_F32, false>), dim3(grid), \
                          dim3(64), 0, st, ka, ws);                                               \
     return hipGetLastError();                                                                    \
   }

@@ -3,8 +3,9 @@
 // per lane), used by the lane-owned kernel and by the mixed-size launch.
 //
 // The arithmetic is the narrow kernel's, operation for operation, so the
-// results are bitwise the same; the mapping differs.  A group of L = 4 lanes
-// holds 4 spots, spot i owned by the group's lane i, and a wavefront 64 spots:
+// results are bitwise the same; the mapping differs.  A group of L lanes (4
+// or 16) holds L spots, spot i owned by the group's lane i, and a wavefront 64
+// spots (or OWN < L spots per group, each owned by L / OWN lanes):
 //
 //  * Each wave step makes L passes.  In pass i the whole group evaluates the
 //    spot of its lane i at that lane's candidate point, exactly as the narrow
@@ -44,12 +45,10 @@ using namespace lm;
 using namespace lg;
 using namespace sep;
 
-constexpr int L = 4;  // lanes per group, and spots per group
-
 // Zeros read in place of the columns outside a spot (one row offset of a
-// 16 x 16 spot at most).  Never written; not const (see the narrow kernel:
+// 32 x 32 spot at most).  Never written; not const (see the narrow kernel:
 // a constant-memory pointer would turn the pixel loads into FLAT loads).
-static __device__ float kZeros[16 * 16];
+static __device__ float kZeros[32 * 32];
 
 // Group totals of a pass that its spot's lane keeps: the evaluation sums, the
 // twelve derivative moments, and chi^2 summed over the pixels when needed.
@@ -83,7 +82,7 @@ struct Src {
   uint32_t step, last;
 };
 
-template <int CPL, int DT>
+template <int L, int CPL, int DT>
 __device__ __forceinline__ Src<CPL> spot_src(const KArgs& ka, int li, int w, int h, int64_t off) {
   constexpr uint32_t esz = DT == SPOTFIT_U16 ? 2u : 4u;
   Src<CPL> s;
@@ -135,10 +134,10 @@ __device__ __forceinline__ double from_lane(double v, int addr) {
 // L lanes per group, CPL columns per lane: spots with w, h <= L * CPL; pixel
 // data type DT.  OWN spots per group: each spot is owned by L / OWN lanes,
 // which take its scalar steps alike (OWN = L: one lane per spot).
-template <int CPL, int DT, int OWN = L>
+template <int L, int CPL, int DT, int OWN = L>
 __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, int32_t* take,
                                           int32_t count, OShared& S) {
-  static_assert(OWN == 4 || OWN == 2, "spots per group");
+  static_assert((L == 4 || L == 16) && L % OWN == 0 && OWN >= 2, "lanes and spots per group");
   constexpr int HM = L * CPL;
   constexpr int SH = L / OWN;  // lanes per spot
   const int lane = __lane_id();
@@ -170,7 +169,7 @@ __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, 
   // loads row r + W into the same slot, and in its last W rows the head of the
   // next loop's spot (the tail source), so that a load is used W rows after it
   // is issued and only W rows take registers.
-  constexpr int W = 4;
+  constexpr int W = L == 16 ? 8 : 4;  // 16-lane groups: 32 rows, loads further ahead
   static_assert(HM % W == 0, "ring rows");
   uint32_t g[CPL][W];
   auto row_loop = [&](const double (&eyl)[CPL], int hs, const Src<CPL>& cur, const Src<CPL>& tail,
@@ -275,11 +274,11 @@ __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, 
     const int ws = from_lane(wv, addr), hs = from_lane(hv, addr);
     const int64_t os = (int64_t)(((uint64_t)(uint32_t)from_lane((int)(uint32_t)off, addr)) |
                                  ((uint64_t)(uint32_t)from_lane((int)(off >> 32), addr) << 32));
-    return spot_src<CPL, DT>(ka, li, ws, hs, os);
+    return spot_src<L, CPL, DT>(ka, li, ws, hs, os);
   };
 
   // no pixels: every column reads the zero block
-  const Src<CPL> none = spot_src<CPL, DT>(ka, li, 0, 0, 0);
+  const Src<CPL> none = spot_src<L, CPL, DT>(ka, li, 0, 0, 0);
 
   reserve(true);
   advance();

@@ -171,13 +171,15 @@ def test_run_to_run_bitwise(gpu):
 # plan override (wide plans 0-4: lanes x columns 8x1, 8x2, 16x1, 16x2, 32x1;
 # narrow plans 5-8: 4x2, 4x4, 8x2, 16x2; one-wave builds 9, 10; the lane-owned
 # plans 11 and 12: 4-lane groups with 4 columns per lane holding 4 spots, one per
-# lane, or 2 spots, a lane pair each; 13: 2 columns per lane, 4 spots per group),
+# lane, or 2 spots, a lane pair each; 13: 2 columns per lane, 4 spots per group;
+# 14, 15: 16-lane groups with 2 columns per lane holding 4 or 16 spots),
 # reproduces the oracle's decisions.
 OWNED_PLANS = [11, 12]
 OWNED_PLAN_8 = 13
+OWNED_PLANS_32 = [14, 15]
 PLANS_UP_TO_8 = [0, 5] + OWNED_PLANS + [OWNED_PLAN_8]
 PLANS_UP_TO_16 = [1, 2, 3, 6, 7, 8, 9] + OWNED_PLANS
-PLANS_UP_TO_32 = [4, 8, 10]
+PLANS_UP_TO_32 = [4, 8, 10] + OWNED_PLANS_32
 
 
 def _plan_fit(batch, cls, plan, side):
@@ -246,6 +248,19 @@ def test_lane_owned_plan_equals_narrow_bitwise(f32, plan):
         assert g_owned["status"][13] == 4  # NOT_CONVERGED on the NaN pixel
 
 
+@pytest.mark.parametrize("plan", OWNED_PLANS_32)
+@pytest.mark.parametrize("f32", [False, True])
+def test_lane_owned_large_plan_equals_narrow_bitwise(f32, plan):
+    # spots up to 32 px (32x32 elliptical): 16-lane lane-owned groups against the
+    # narrow 16x2 plan
+    b = _troubled(spotgen.workload("precision_32x32_ell", n=10007), f32)
+    g_narrow = _plan_fit(b, 2, 8, 32)
+    g_owned = _plan_fit(b, 2, plan, 32)
+    for k in g_narrow:
+        np.testing.assert_array_equal(g_owned[k], g_narrow[k], err_msg=k)
+    assert (g_owned["status"] == 5).sum() == 3
+
+
 @pytest.mark.parametrize("f32", [False, True])
 def test_lane_owned_small_plan_equals_narrow_bitwise(f32):
     # spots up to 8 px: the lane-owned plan with 2 columns per lane against the
@@ -260,12 +275,14 @@ def test_lane_owned_small_plan_equals_narrow_bitwise(f32):
 
 
 # mixed-size plans: 4 = narrow classes (4x2, 4x4, 16x2); 6 = the same with the
-# lane-owned mapping for the <= 16 px class
-NARROW_MIXED_PLAN, OWNED_MIXED_PLAN = 4, 6
+# lane-owned mapping for the <= 16 px class; 7 = lane-owned for the <= 32 px
+# class too
+NARROW_MIXED_PLAN, OWNED_MIXED_PLANS = 4, [6, 7]
 
 
+@pytest.mark.parametrize("owned_plan", OWNED_MIXED_PLANS)
 @pytest.mark.parametrize("raw", [False, True])
-def test_lane_owned_mixed_plan_equals_narrow_mixed_bitwise(raw):
+def test_lane_owned_mixed_plan_equals_narrow_mixed_bitwise(raw, owned_plan):
     # one persistent launch over spots of 7..32 px: the lane-owned class gives the
     # narrow class's bits (a launch computing its start values keeps the narrow
     # mapping for that class)
@@ -278,7 +295,7 @@ def test_lane_owned_mixed_plan_equals_narrow_mixed_bitwise(raw):
     dev = torch.device("cuda:0")
     up = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     outs = []
-    for plan in (NARROW_MIXED_PLAN, OWNED_MIXED_PLAN):
+    for plan in (NARROW_MIXED_PLAN, owned_plan):
         os.environ["SPOTFIT_MIXED_PLAN"] = str(plan)
         try:
             ctx = sf.Context(0)
