@@ -795,7 +795,7 @@ int wide_plan_count() { return 5; }
 
 // The lane-owned plans: lanes per group, columns per lane, spots per group.
 constexpr int kOwnedPlans = 5;
-static const int kOwned[kOwnedPlans][3] = {{4, 4, 4}, {4, 4, 2}, {4, 2, 4}, {16, 2, 4}, {16, 2, 16}};
+static const int kOwned[kOwnedPlans][3] = {{4, 4, 4}, {4, 4, 2}, {4, 2, 4}, {16, 2, 4}, {16, 2, 8}};
 
 int group_plan_count() { return wide_plan_count() + narrow_plan_count() + 2 + kOwnedPlans; }
 

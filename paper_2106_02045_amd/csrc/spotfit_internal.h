@@ -125,7 +125,7 @@ const void* narrow_mixed_kernel_symbol(int plan);
 // the lane-owned kernel (spots up to 16 x 16 pixels): resets ka.queue, then
 // fits ka.n < 2^31 spots handed out through that counter; reads ka.init
 // lanes per group, columns per lane (spots up to lanes * cpl px), spots per
-// group; built: (4, 4, 4), (4, 4, 2), (4, 2, 4), (16, 2, 4), (16, 2, 16)
+// group; built: (4, 4, 4), (4, 4, 2), (4, 2, 4), (16, 2, 4), (16, 2, 8)
 const void* owned_kernel_symbol(int lanes, int cpl, int own);
 hipError_t launch_owned_kernel(int lanes, int cpl, int own, const KArgs& ka, int grid, hipStream_t st);
 // the mixed-size plan that gives `plan`'s bits with narrow mappings only (the

@@ -27,10 +27,10 @@ __global__ void owned_queue_reset_kernel(int32_t* take) {
 // pixels) holding 4 spots (one per lane, 64 per wavefront) or 2 (a lane pair
 // per spot: half the pixels in flight, twice the scalar work per spot); 4-lane
 // groups with 2 columns per lane (up to 8 x 8), 4 spots; 16-lane groups with 2
-// columns per lane (up to 32 x 32) holding 4 spots (4 lanes per spot) or 16.
+// columns per lane (up to 32 x 32) holding 4 spots (4 lanes per spot) or 8.
 constexpr int kOwnedWpe = 2;
 
-#define SF_OWNED_KERNELS(X) X(4, 4, 4) X(4, 4, 2) X(4, 2, 4) X(16, 2, 4) X(16, 2, 16)
+#define SF_OWNED_KERNELS(X) X(4, 4, 4) X(4, 4, 2) X(4, 2, 4) X(16, 2, 4) X(16, 2, 8)
 
 const void* owned_kernel_symbol(int lanes, int cpl, int own) {
 #define SF_OSYM(L, C, O)                               \

@@ -172,7 +172,7 @@ def test_run_to_run_bitwise(gpu):
 # narrow plans 5-8: 4x2, 4x4, 8x2, 16x2; one-wave builds 9, 10; the lane-owned
 # plans 11 and 12: 4-lane groups with 4 columns per lane holding 4 spots, one per
 # lane, or 2 spots, a lane pair each; 13: 2 columns per lane, 4 spots per group;
-# 14, 15: 16-lane groups with 2 columns per lane holding 4 or 16 spots),
+# 14, 15: 16-lane groups with 2 columns per lane holding 4 or 8 spots),
 # reproduces the oracle's decisions.
 OWNED_PLANS = [11, 12]
 OWNED_PLAN_8 = 13
