@@ -743,6 +743,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   }
 }
 
+// Whether the lane-owned classes of a mixed-size launch skip the passes of
+// empty slots: not taken, since a wavefront's last spots of one class overlap
+// the other wavefronts' spots of the next (skipping measured 0.8 % slower on
+// 2M spots of sides 7..32).
+constexpr bool kMixedSkip = false;
+
 // A mixed-size launch whose <= 16 px class runs the lane-owned mapping (4-lane
 // groups of 4 spots, CPL1 columns per lane), and with OWN2 > 0 its <= 32 px
 // class too (L2-lane groups of OWN2 spots); a launch that computes its start
@@ -772,10 +778,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
       if constexpr (RAW)
         fit_narrow<4, CPL1, DT, RAW>(ka, SpotQueue{list, take, count}, lds.n.sts, lds.n.cinit);
       else
-        own::fit_owned<4, CPL1, DT>(ka, list, take, count, lds.o);
+        own::fit_owned<4, CPL1, DT, 4, kMixedSkip>(ka, list, take, count, lds.o);
     } else {
       if constexpr (OWN2 > 0 && !RAW)
-        own::fit_owned<L2, C2, DT, OWN2>(ka, list, take, count, lds.o);
+        own::fit_owned<L2, C2, DT, OWN2, kMixedSkip>(ka, list, take, count, lds.o);
       else
         fit_narrow<L2, C2, DT, RAW>(ka, SpotQueue{list, take, count}, lds.n.sts, lds.n.cinit);
     }

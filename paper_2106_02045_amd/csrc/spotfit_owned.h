@@ -133,8 +133,9 @@ __device__ __forceinline__ double from_lane(double v, int addr) {
 // wavefront takes positions from the counter `take` a chunk of 64 at a time.
 // L lanes per group, CPL columns per lane: spots with w, h <= L * CPL; pixel
 // data type DT.  OWN spots per group: each spot is owned by L / OWN lanes,
-// which take its scalar steps alike (OWN = L: one lane per spot).
-template <int L, int CPL, int DT, int OWN = L>
+// which take its scalar steps alike (OWN = L: one lane per spot).  SKIP: a
+// step runs only the passes of slots that hold a spot in some group.
+template <int L, int CPL, int DT, int OWN = L, bool SKIP = true>
 __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, int32_t* take,
                                           int32_t count, OShared& S) {
   static_assert((L == 4 || L == 16) && L % OWN == 0 && OWN >= 2, "lanes and spots per group");
@@ -280,10 +281,35 @@ __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, 
   // no pixels: every column reads the zero block
   const Src<CPL> none = spot_src<L, CPL, DT>(ka, li, 0, 0, 0);
 
+  // The passes of a step: one per slot that holds a spot in some group, in slot
+  // order, packed 4 bits each (as a wavefront's spots run out, its steps skip
+  // the slots that no group uses).
+  constexpr uint64_t kSlot0 = [] {
+    uint64_t m = 0;
+    for (int gi = 0; gi < 64 / L; ++gi) m |= uint64_t(1) << (gi * L);
+    return m;
+  }();
+  int npass = 0;
+  auto pass_order = [&]() -> uint32_t {
+    const uint64_t lv = __builtin_amdgcn_ballot_w64(s >= 0 && lead);
+    uint32_t ord = 0;
+    int n = 0;
+#pragma unroll
+    for (int p = 0; p < OWN; ++p) {
+      if (!SKIP || (lv & (kSlot0 << (p * SH)))) {
+        ord |= uint32_t(p) << (4 * n);
+        ++n;
+      }
+    }
+    npass = n;
+    return ord;
+  };
+
   reserve(true);
   advance();
   reserve(true);
-  load_head<CPL, W, DT>(g, src_of(0));
+  uint32_t ord = pass_order();
+  load_head<CPL, W, DT>(g, src_of(int(ord & 15u)));
 
   while (__builtin_amdgcn_ballot_w64(s >= 0) != 0) {
     const int wv = s >= 0 ? w : 0, hv = s >= 0 ? h : 0;
@@ -294,7 +320,8 @@ __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, 
 
     // ================= passes: the group evaluates each of its spots =================
 #pragma unroll 1
-    for (int p = 0; p < OWN; ++p) {
+    for (int i = 0; i < npass; ++i) {
+      const int p = int((ord >> (4 * i)) & 15u);
       const int addr = gaddr + ((p * SH) << 2);
       const bool mine = slot == p;
       const int ws = from_lane(wv, addr), hs = from_lane(hv, addr);
@@ -303,9 +330,9 @@ __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, 
       const double x = from_lane(pc[0], addr), y = from_lane(pc[1], addr);
       const double p2 = from_lane(pc[2], addr), p3 = from_lane(pc[3], addr);
       const double gs_spot = from_lane(Gs, addr);
-      const bool more = p + 1 < OWN;
+      const bool more = i + 1 < npass;
       const Src<CPL> cur = src_of(p);
-      const Src<CPL> nx = more ? src_of(p + 1) : none;
+      const Src<CPL> nx = more ? src_of(int((ord >> (4 * i + 4)) & 15u)) : none;
 
       // trial evaluation at the spot's point (Eqs. 2, 5, 6, 10)
       const double hx = -0.5 * rcp_nr(p2 * p2);
@@ -634,7 +661,8 @@ __device__ __forceinline__ void fit_owned(const KArgs& ka, const int32_t* list, 
 
     // pixels of the next step's first pass (its spot may be new), issued before
     // the normal equations and the solve so that those cover their latency
-    load_head<CPL, W, DT>(g, src_of(0));
+    ord = pass_order();
+    load_head<CPL, W, DT>(g, src_of(int(ord & 15u)));
 
     // ================= normal equations at pc (Eqs. 7-9, 11) =================
     if (do_grad) {
