@@ -112,9 +112,11 @@ typedef enum {
 typedef enum {
   SPOTFIT_PLAN_THROUGHPUT = 0, /* default: the most spots per second for batches that fill
                                   the GPU.  Spots up to 16x16 px: 4-lane groups that fit 4
-                                  spots at once, one per lane, when the batch gives every
-                                  resident lane at least 4 spots, else 4 lanes per spot (the
-                                  same bits); larger spots: 16 lanes per spot            */
+                                  spots at once, one per lane; larger spots: 16-lane groups
+                                  of 4 spots.  A batch too small to give every resident spot
+                                  slot 1.5-2.5 spots (about 200k-330k spots up to 16 px, 80k
+                                  above, on 256 CUs) takes 4 or 16 lanes per spot instead
+                                  (the same bits)                                        */
   SPOTFIT_PLAN_LATENCY = 1     /* one lane per column (8, 16 or 32 lanes per spot): each
                                   evaluation step is shorter, so a batch too small to
                                   fill the GPU (a camera frame) finishes sooner; results

@@ -377,10 +377,21 @@ int check_call(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
 // of the wide mixed-size plan (measured: faster up to 40,000 spots of the
 // serving and mixed workloads, slower from 400,000).
 constexpr int64_t kLeanMaxSpots = 65536;
-// The lane-owned plans hold 64 (or 32) spots per wavefront and make a pass per
-// spot of a group each step: they pay off when every resident lane fits several
-// spots in turn (measured on 15x15 and 7x7 spots: slower up to 262k spots,
-// 19-26 % faster at 1M); a smaller batch takes the narrow plan of the same bits.
+// The lane-owned plans hold 16-64 spots per wavefront and make a pass per
+// spot of a group each step: they pay off when every resident spot slot fits
+// several spots in turn; a smaller batch takes the narrow plan of the same
+// bits.  Spots per resident slot from which a uniform launch takes the
+// lane-owned plan, in halves: the crossovers measured against the narrow
+// plans (15x15: between 262k and 393k spots, 2.0-3.0 per slot; 7x7: between
+// 131k and 197k, 1.0-1.5; 32x32: between 66k and 131k, 2.0-4.0); plans that
+// are not defaults keep 4.
+int64_t owned_min_halves(int plan) {
+  if (plan == sf::owned_plan_id(4, 4, 4) || plan == sf::owned_plan_id(16, 2, 4)) return 5;
+  if (plan == sf::owned_plan_id(4, 2, 4)) return 3;
+  return 8;
+}
+// The same rule for a mixed-size launch with lane-owned classes (over the
+// whole batch; measured at 2M spots only).
 constexpr int64_t kOwnedMinSpotsPerLane = 4;
 
 // Enqueue one fit with validated options o and n > 0.  init_out not NULL (with
@@ -461,7 +472,7 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
       int ol = 0, oc = 0;
       sf::group_plan_shape(plan, &ol, &oc);
       const int64_t lanes_resident = (int64_t)ctx->n_cu * ctx->occ_plan[plan] * (64 / ol);
-      if (init_out || (!ctx->plan_forced[cls] && n < kOwnedMinSpotsPerLane * lanes_resident))
+      if (init_out || (!ctx->plan_forced[cls] && 2 * n < owned_min_halves(plan) * lanes_resident))
         plan = sf::plan_for_raw(plan);
     }
     int lanes = 0, cpl = 0;
