@@ -257,10 +257,13 @@ int spotfit_peak_init(spotfit_ctx_t* ctx, const void* data, int32_t dtype,
 /* Raw spots in, fits out, in one launch: the start values of
  * spotfit_moment_init and the fit from them (the paper leaves start values to
  * the caller, Results section; its fit is the Fit2DGaussian algorithm with
- * Eqs. 5-14).  With opt->precision SPOTFIT_PREC_FP64 the fit kernel's own
- * lane groups compute each spot's start values before they fit it, so no
+ * Eqs. 5-14).  With opt->precision SPOTFIT_PREC_FP64 and a batch that the
+ * narrow or wide plans fit (the latency hint, or too few spots for the
+ * lane-owned plans of SPOTFIT_PLAN_THROUGHPUT), the fit kernel's own lane
+ * groups compute each spot's start values before they fit it, so no
  * start-value pass and no round trip through memory sits between frame and
- * fit; with the other precisions a start-value launch precedes the fit.
+ * fit; a batch that takes a lane-owned plan, and the other precisions, get a
+ * start-value launch first (for the lane-owned plans the faster way).
  * init_out float[n][4] (device, caller-owned, required) receives the start
  * values each fit began from (NaN for the shapes spotfit_moment_init rejects,
  * whose fits end as BAD_INPUT).  They equal spotfit_moment_init's up to the

@@ -519,14 +519,36 @@ int launch_fit(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfi
   return SPOTFIT_OK;
 }
 
-// Enqueue start values and fit (validated options o, n > 0): in the fit's own
-// launch for the separable double-precision kernels, else a start-value
-// launch first (the other kernels read their start values from memory).
+// Whether a fit of n spots with start values in memory (validated options o)
+// takes a lane-owned plan: the plan choice of launch_fit.
+bool takes_owned(const spotfit_ctx_t* ctx, int64_t n, const spotfit_options_t& o) {
+  if (o.precision != SPOTFIT_PREC_FP64 || o.plan_hint == SPOTFIT_PLAN_LATENCY) return false;
+  if (o.schedule == SPOTFIT_SCHEDULE_MIXED) {
+    const int mplan = ctx->mixed_plan;
+    return sf::mixed_plan_narrow(mplan) != mplan &&
+           (ctx->mixed_forced || n >= kOwnedMinSpotsPerLane * (int64_t)ctx->n_cu * ctx->occ_mixed[mplan] * 64);
+  }
+  const int cls = o.max_side <= 8 ? 0 : o.max_side <= 16 ? 1 : 2;
+  const int plan = ctx->plan_for_class[cls];
+  if (sf::plan_for_raw(plan) == plan) return false;
+  int ol = 0, oc = 0;
+  sf::group_plan_shape(plan, &ol, &oc);
+  const int64_t lanes_resident = (int64_t)ctx->n_cu * ctx->occ_plan[plan] * (64 / ol);
+  return ctx->plan_forced[cls] || 2 * n >= owned_min_halves(plan) * lanes_resident;
+}
+
+// Enqueue start values and fit (validated options o, n > 0).  The separable
+// double-precision kernels of the narrow and wide plans compute them in the
+// fit's own launch; a batch that takes a lane-owned plan, and the other
+// kernels, get a start-value launch first and read them from memory (the
+// lane-owned fit with its start values from memory is the faster of the two
+// there: 1M 15x15 1.54 against 1.61 ms, 1M 32x32 5.14 against 6.14, 2M mixed
+// sizes 6.45 against 7.11; the same bits either way).
 int launch_raw(spotfit_ctx_t* ctx, const void* data, int32_t dtype, const spotfit_shape_t* sizes,
                const int64_t* offsets, int64_t n, const spotfit_options_t& o, float* init_out,
                float* params_out, float* chi2_out, int32_t* iters_out, int32_t* status_out,
                int32_t* evals_out, void* stream, const sf::MixedWs* own_ws = nullptr) {
-  if (o.precision == SPOTFIT_PREC_FP64)
+  if (o.precision == SPOTFIT_PREC_FP64 && !takes_owned(ctx, n, o))
     return launch_fit(ctx, data, dtype, sizes, offsets, nullptr, n, o, params_out, chi2_out,
                       iters_out, status_out, evals_out, stream, init_out, nullptr, own_ws);
   const hipError_t e = sf::launch_start_values(sf::kInitMoments, data, dtype, sizes, offsets, n,
