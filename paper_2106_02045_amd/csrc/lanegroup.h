@@ -85,6 +85,9 @@ __device__ __forceinline__ int gbcast_i(int v) {
 
 template <int L, int Q>
 __device__ __forceinline__ double gbcast(double v) {
+  // a 16-lane group is a DPP row: one 64-bit move broadcasts its lane Q
+  // (row_newbcast, the one DPP control of gfx950's 64-bit moves)
+  if constexpr (L == 16) return __builtin_amdgcn_update_dpp(0.0, v, 0x150 | Q, 0xF, 0xF, false);
   int2 u = *reinterpret_cast<int2*>(&v);
   int2 r = make_int2(gbcast_i<L, Q>(u.x), gbcast_i<L, Q>(u.y));
   return *reinterpret_cast<double*>(&r);
